@@ -1,0 +1,179 @@
+/*
+ * chisao.h -- C ABI of libchisao, the MI355X (gfx950) implementation of the
+ * ChiSao per-cycle population update (Wolfson, "ChiSao: A GPU-Native Parallel
+ * Optimizer for Multimodal Black-Box Functions via Convergence-Anticonvergence
+ * Oscillation").
+ *
+ * The library finds the significant modes of a mixture log-density
+ * f : Theta -> R on a box Theta (Sec. 3.1, eq. 1): a population of N samples
+ * goes through n_osc oscillation cycles of six phases (Sec. 3.2, Algorithm 1):
+ * batched L-BFGS ascent, the stick test, L-infinity deduplication, Repulse
+ * Monkey / Golden Rooster reseeding, Hands Like Clouds smoothed ascent and
+ * momentum anti-convergence.  Every phase runs in HIP kernels on one GPU.
+ *
+ * Conventions for every entry point:
+ *  - Return value: CHISAO_OK (0) or a negative CHISAO_E_* code; the message of
+ *    the most recent failure on the calling thread is chisao_last_error().
+ *  - "host" pointers are read (or written) before the call returns; "device"
+ *    pointers must be device memory of the GPU that was current when the handle
+ *    was created (for example a torch tensor's data_ptr()).
+ *  - Arrays are dense, row-major, float32 unless stated; a sample's d
+ *    coordinates are contiguous.
+ *  - No partial results are written when a call fails.
+ *  - A handle must not be used from two threads at once; distinct handles are
+ *    independent.
+ */
+#ifndef CHISAO_H
+#define CHISAO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CHISAO_OK 0
+#define CHISAO_E_INVAL (-1)  /* bad sizes, d > 64, N < 1, lo >= hi, non-finite or non-SPD parameters */
+#define CHISAO_E_NOMEM (-2)  /* device allocation failed */
+#define CHISAO_E_DEVICE (-3) /* a HIP call failed; see chisao_last_error() */
+#define CHISAO_E_STATE (-4)  /* cycle requested past n_osc, or call not valid in this state */
+#define CHISAO_E_RANGE (-5)  /* output capacity too small; the required size is reported */
+
+#define CHISAO_GAUSS 0     /* Gaussian mixture log-density (Appendix D, with full precision matrices) */
+#define CHISAO_STUDENT_T 1 /* multivariate Student-t mixture log-density */
+
+#define CHISAO_GRAD_FD 0      /* central finite differences, 2d evaluations per gradient (Sec. 3.1, Sec. 5) */
+#define CHISAO_GRAD_ADJOINT 1 /* analytic reverse-mode gradient fused with the value */
+
+/* Mixture objective f(x) = log sum_k w_k p_k(x) on the box [lo, hi].
+ * p_k is N(mu_k, prec_k^-1) (Gaussian) or the Student-t density with nu
+ * degrees of freedom and scale matrix prec_k^-1.  All arrays are host memory,
+ * copied by chisao_init. */
+typedef struct {
+    int32_t family;      /* CHISAO_GAUSS or CHISAO_STUDENT_T */
+    int32_t d;           /* dimension, 1..64 */
+    int32_t K;           /* number of components, >= 1 */
+    float nu;            /* Student-t degrees of freedom (> 0), ignored for Gaussians */
+    const float *log_w;  /* [K] log mixture weights */
+    const float *mu;     /* [K*d] component centres */
+    const float *prec;   /* [K*d*d] exactly symmetric positive-definite precision (inverse covariance / inverse scale) */
+    const float *lo;     /* [d] lower box bounds */
+    const float *hi;     /* [d] upper box bounds, hi > lo */
+    float noise_sigma;   /* additive evaluation noise; must be 0 in this version */
+} chisao_problem;
+
+/* Schedule and hyperparameters (Sec. 3.6, Table 1).  A value <= 0 in a field
+ * marked "auto" selects the rule named next to it. */
+typedef struct {
+    int32_t N;          /* population size, >= 1 */
+    int32_t m;          /* L-BFGS memory, 1..32 */
+    int32_t n_osc;      /* oscillation cycles */
+    int32_t n_conv;     /* L-BFGS iterations per cycle; auto: max(10, ceil(3 log2 d)) */
+    int32_t n_anti;     /* anti-convergence steps */
+    int32_t n_cloud;    /* Hands Like Clouds steps */
+    int32_t M;          /* probes per smoothed gradient, 1..32 */
+    float eps_grad;     /* stick threshold on the gradient sup-norm */
+    float eps_dup;      /* L-infinity deduplication radius */
+    float log_delta;    /* log of the quality threshold delta (log 0.1 by default) */
+    float momentum;     /* anti-convergence momentum mu */
+    float alpha;        /* step length of both exploration phases; auto: sigma / mean |grad| */
+    float sigma;        /* smoothing scale; auto: sigma_c * pooled std of unfrozen samples */
+    float sigma_c;      /* the constant c of the sigma rule */
+    int32_t grad_mode;  /* CHISAO_GRAD_FD or CHISAO_GRAD_ADJOINT */
+    float fd_h;         /* finite-difference step; auto: h_j = 2^-8 max(1, |x_j|) */
+    float ls_c1;        /* Armijo constant of the backtracking line search */
+    int32_t ls_max;     /* backtracking trials t = 1, 1/2, ..., 2^-(ls_max-1); 1..16 */
+    float curv_eps;     /* a pair is stored when s'y > curv_eps |s| |y| */
+    int32_t gate_reps;  /* reserved (noisy objectives); must be 0 */
+    uint32_t phase_mask;/* bit p enables phase p for p = 3..6 (ablation hook); 0x7E = all */
+    uint64_t seed;      /* key of every random stream */
+    uint32_t problem_id;/* mixed into the key, so problems draw independent streams */
+} chisao_config;
+
+/* Per-cycle statistics (host struct). */
+typedef struct {
+    int32_t k;          /* 1-based index of the cycle these figures belong to */
+    float f_max;        /* largest value over active samples after Phase 1 */
+    int32_t n_stuck;    /* samples passing the stick test (before deduplication) */
+    int32_t K_lost;     /* duplicates removed by Phase 3 */
+    int32_t n_modes;    /* stuck samples surviving deduplication */
+    int32_t reseed_kind;/* 0 none, 1 Repulse Monkey, 2 Golden Rooster, 3 slots deactivated */
+    int32_t n_free;     /* unfrozen samples available as Repulse Monkey origins */
+    int32_t n_unfrozen; /* samples moved by Phases 5-6 */
+    int32_t n_active;   /* samples still in use */
+    float sigma;        /* smoothing scale used in Phase 5 */
+    float alpha_c;      /* Hands Like Clouds step length */
+    float alpha_a;      /* anti-convergence step length */
+    int32_t ls_fail;    /* line searches that failed during Phase 1 */
+    int32_t evals;      /* objective evaluations (points) during the cycle */
+} chisao_cycle_stats;
+
+/* Host view of the population state for chisao_get_state / chisao_set_state.
+ * Each pointer may be NULL to skip that array. */
+typedef struct {
+    float *X;           /* [N*d] positions */
+    float *F;           /* [N] values after Phase 1 (get only) */
+    float *G;           /* [N*d] gradients after Phase 1 (get only) */
+    uint8_t *stuck;     /* [N] stuck flags (after deduplication) */
+    uint8_t *active;    /* [N] slot-in-use flags */
+    uint8_t *stuck_pre; /* [N] stick decisions before deduplication (get only) */
+    uint8_t *removed;   /* [N] deduplication decisions (get only) */
+    uint8_t *trace;     /* [(n_conv+1)*N] per-iteration L-BFGS decision codes of the last Phase 1 (get only):
+                           0xFF not iterated; bits 0-3 accepted backtracking index (15 = failed);
+                           bit 4 pair stored; bit 5 converged; bit 6 direction reset */
+    int32_t k;          /* cycles completed */
+    int32_t gr_disabled, gr_fail, gr_used_last, gr_prev_modes; /* Golden Rooster generation state */
+} chisao_state;
+
+typedef struct chisao_ctx *chisao_handle;
+
+/* Create an optimizer for one problem (Sec. 3.1: f, the population, the
+ * schedule).  x0_dev: device [N*d] starting population inside the box, or NULL
+ * for a uniform draw in the box.  hip_stream: the hipStream_t all work is
+ * enqueued on (NULL = default stream).  Allocates the library-owned device
+ * workspace, copies every input, and synchronizes before returning. */
+int chisao_init(chisao_handle *out, const chisao_problem *p, const chisao_config *c, const float *x0_dev,
+                void *hip_stream);
+
+/* Run n_cycles oscillation cycles (Algorithm 1 body).  Phases 4-6 are
+ * skipped in cycle n_osc.  Work is enqueued asynchronously; when stats_host is
+ * not NULL the call synchronizes and fills n_cycles entries.  Running past
+ * n_osc fails with CHISAO_E_STATE and runs nothing. */
+int chisao_cycle(chisao_handle h, int n_cycles, chisao_cycle_stats *stats_host);
+
+/* The estimated mode set {x_i : stuck_i} (Algorithm 1 return value):
+ * synchronizes, then writes the stuck active samples in ascending index to
+ * x_out (host [cap*d]) and f_out (host [cap], may be NULL).  *n_out receives
+ * the count; if cap is smaller, nothing is written and CHISAO_E_RANGE is
+ * returned.  problem must be 0. */
+int chisao_modes(chisao_handle h, int problem, float *x_out, float *f_out, int cap, int *n_out);
+
+/* Copy the state to / from host memory (synchronizes).  set_state writes X,
+ * stuck, active, k and the Golden Rooster state; F, G and the decision arrays
+ * are recomputed by the next cycle. */
+int chisao_get_state(chisao_handle h, chisao_state *s);
+int chisao_set_state(chisao_handle h, const chisao_state *s);
+
+/* Run a subset of the phases of cycle k+1 on the current state without
+ * advancing k (test hook for per-phase parity).  phase_mask bit p selects
+ * phase p (1..6); phases run in ascending order.  Synchronizes. */
+int chisao_run_phases(chisao_handle h, uint32_t phase_mask);
+
+/* Batched objective on caller memory (Sec. 3.1 objective, with the gradient
+ * the method would use): X_dev device [B*d]; f_dev device [B] (may be NULL);
+ * G_dev device [B*d] (may be NULL).  grad_mode selects the adjoint kernel or
+ * central differences (fd_h of the handle's config).  Enqueued on the
+ * handle's stream; does not synchronize. */
+int chisao_eval(chisao_handle h, const float *X_dev, int B, float *f_dev, float *G_dev, int grad_mode);
+
+void chisao_destroy(chisao_handle h);
+
+/* Message of the last failure on this thread ("" if none); valid until the
+ * next library call on the same thread. */
+const char *chisao_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CHISAO_H */

@@ -1,0 +1,139 @@
+"""Python face of libchisao: marshals arguments for the C ABI; all work runs in its kernels.
+
+``Optimizer`` wraps one handle.  ``problem`` and ``config`` may be any objects
+with the fields of ``chisao_problem`` / ``chisao_config`` (numpy arrays for the
+problem arrays).  torch supplies device memory and the stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def _f32(a, shape):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float32).reshape(shape))
+
+
+@dataclass
+class ModeSet:
+    X: np.ndarray
+    F: np.ndarray
+
+
+class Optimizer:
+    def __init__(self, problem, config, x0: torch.Tensor | np.ndarray | None = None, device=None, stream=None):
+        self.lib = L.load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("libchisao needs a ROCm GPU (torch.cuda.is_available() is False)")
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        d, K = int(problem.d), int(problem.K)
+        self.d, self.K, self.N = d, K, int(config.N)
+        self._keep = dict(
+            log_w=_f32(problem.log_w, (K,)), mu=_f32(problem.mu, (K, d)), prec=_f32(problem.prec, (K, d, d)),
+            lo=_f32(problem.lo, (d,)), hi=_f32(problem.hi, (d,)))
+        k = self._keep
+        self.cp = L.Problem(int(problem.family), d, K, float(getattr(problem, "nu", 0.0)), k["log_w"].ctypes.data,
+                            k["mu"].ctypes.data, k["prec"].ctypes.data, k["lo"].ctypes.data, k["hi"].ctypes.data,
+                            float(getattr(problem, "noise_sigma", 0.0)))
+        c = config
+        self.cc = L.Config(int(c.N), int(c.m), int(c.n_osc), int(c.n_conv), int(c.n_anti), int(c.n_cloud), int(c.M),
+                           float(c.eps_grad), float(c.eps_dup), float(c.log_delta), float(c.momentum),
+                           float(c.alpha), float(c.sigma), float(c.sigma_c), int(c.grad_mode), float(c.fd_h),
+                           float(c.ls_c1), int(c.ls_max), float(c.curv_eps), int(c.gate_reps), int(c.phase_mask),
+                           int(c.seed), int(c.problem_id))
+        self.n_conv = int(c.n_conv) if int(c.n_conv) > 0 else max(10, int(np.ceil(3 * np.log2(d) - 1e-9)))
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        x0_ptr = None
+        if x0 is not None:
+            x0t = torch.as_tensor(np.asarray(x0, np.float32) if isinstance(x0, np.ndarray) else x0)
+            self._x0 = x0t.to(self.device, torch.float32).contiguous().reshape(self.N, d)
+            x0_ptr = self._x0.data_ptr()
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            L.check(self.lib.chisao_init(C.byref(h), C.byref(self.cp), C.byref(self.cc), x0_ptr,
+                                         self.stream.cuda_stream), "chisao_init")
+        self.h = h
+
+    # ------------------------------------------------------------------
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.chisao_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # ------------------------------------------------------------------
+    def cycle(self, n: int = 1, stats: bool = False):
+        arr = (L.CycleStats * max(n, 1))() if stats else None
+        L.check(self.lib.chisao_cycle(self.h, n, arr), "chisao_cycle")
+        if not stats:
+            return None
+        return [{f: getattr(arr[i], f) for f, _ in L.CycleStats._fields_} for i in range(n)]
+
+    def run_phases(self, mask: int):
+        L.check(self.lib.chisao_run_phases(self.h, mask), "chisao_run_phases")
+
+    def modes(self) -> ModeSet:
+        n = C.c_int(0)
+        rc = self.lib.chisao_modes(self.h, 0, None, None, 0, C.byref(n))
+        if rc not in (L.OK, L.E_RANGE):
+            L.check(rc, "chisao_modes")
+        X = np.zeros((n.value, self.d), np.float32)
+        F = np.zeros(n.value, np.float32)
+        L.check(self.lib.chisao_modes(self.h, 0, X.ctypes.data, F.ctypes.data, n.value, C.byref(n)), "chisao_modes")
+        return ModeSet(X, F)
+
+    def get_state(self) -> dict:
+        N, d = self.N, self.d
+        out = dict(X=np.zeros((N, d), np.float32), F=np.zeros(N, np.float32), G=np.zeros((N, d), np.float32),
+                   stuck=np.zeros(N, np.uint8), active=np.zeros(N, np.uint8), stuck_pre=np.zeros(N, np.uint8),
+                   removed=np.zeros(N, np.uint8), trace=np.zeros((self.n_conv + 1, N), np.uint8))
+        s = L.State(*[out[f].ctypes.data for f in ("X", "F", "G", "stuck", "active", "stuck_pre", "removed", "trace")])
+        L.check(self.lib.chisao_get_state(self.h, C.byref(s)), "chisao_get_state")
+        out.update(k=s.k, gr_disabled=s.gr_disabled, gr_fail=s.gr_fail, gr_used_last=s.gr_used_last,
+                   gr_prev_modes=s.gr_prev_modes)
+        return out
+
+    def set_state(self, X=None, stuck=None, active=None, k=None, gr=None):
+        cur = self.get_state()
+        keep = []
+
+        def ptr(a, dt, shape):
+            if a is None:
+                return None
+            a = np.ascontiguousarray(np.asarray(a, dt).reshape(shape))
+            keep.append(a)
+            return a.ctypes.data
+
+        gr = gr or {}
+        s = L.State(ptr(X, np.float32, (self.N, self.d)), None, None, ptr(stuck, np.uint8, (self.N,)),
+                    ptr(active, np.uint8, (self.N,)), None, None, None, cur["k"] if k is None else int(k),
+                    gr.get("gr_disabled", cur["gr_disabled"]), gr.get("gr_fail", cur["gr_fail"]),
+                    gr.get("gr_used_last", cur["gr_used_last"]), gr.get("gr_prev_modes", cur["gr_prev_modes"]))
+        L.check(self.lib.chisao_set_state(self.h, C.byref(s)), "chisao_set_state")
+
+    def eval(self, X: torch.Tensor, grad_mode: int = L.GRAD_ADJOINT, want_f: bool = True, want_g: bool = True):
+        """Objective (and gradient) at the rows of X (a float32 CUDA tensor)."""
+        X = X.to(self.device, torch.float32).contiguous()
+        B = X.shape[0]
+        f = torch.empty(B, device=self.device, dtype=torch.float32) if want_f else None
+        G = torch.empty(B, self.d, device=self.device, dtype=torch.float32) if want_g else None
+        with torch.cuda.stream(self.stream):
+            L.check(self.lib.chisao_eval(self.h, X.data_ptr(), B, f.data_ptr() if f is not None else None,
+                                         G.data_ptr() if G is not None else None, grad_mode), "chisao_eval")
+        return f, G

@@ -1,0 +1,157 @@
+// Device-side definitions shared by the libchisao kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace chisao {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------------------
+// Counter-based random streams: Philox4x32-10 (Salmon, Moraes, Dror, Shaw,
+// SC'11), ten rounds with the Weyl key schedule.  The counter words are
+// (index, cycle, consumer << 24 | step << 16 | sub, block); the key is the
+// 64-bit seed with the problem id folded into the high word.
+// ---------------------------------------------------------------------------
+enum Stream : uint32_t { kInit = 0, kRM = 4, kGR = 5, kHLC = 6 };
+
+__device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                        uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+        const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+        const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+    }
+    return make_uint4(c0, c1, c2, c3);
+}
+
+// (top 24 bits + 1/2) * 2^-24: exact in float, strictly inside (0, 1).
+__device__ __forceinline__ float u01(uint32_t a) { return ((float)(a >> 8) + 0.5f) * (1.0f / 16777216.0f); }
+
+// Box-Muller on the uniform pairs (o.x, o.y) and (o.z, o.w).
+__device__ __forceinline__ void box_muller4(uint4 o, float z[4]) {
+    float s, c;
+    float r = sqrtf(-2.0f * logf(u01(o.x)));
+    sincospif(2.0f * u01(o.y), &s, &c);
+    z[0] = r * c;
+    z[1] = r * s;
+    r = sqrtf(-2.0f * logf(u01(o.z)));
+    sincospif(2.0f * u01(o.w), &s, &c);
+    z[2] = r * c;
+    z[3] = r * s;
+}
+
+// integer in [0, n): high word of the 64-bit product
+__device__ __forceinline__ uint32_t uint_below(uint32_t a, uint32_t n) { return __umulhi(a, n); }
+
+// ---------------------------------------------------------------------------
+// Wave-wide reductions (all 64 lanes participate and receive the result).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+__device__ __forceinline__ float wave_min(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+// Total order on floats as signed ints, for exact atomic max.
+__device__ __forceinline__ int float_to_ordered(float f) {
+    int i = __float_as_int(f);
+    return i >= 0 ? i : i ^ 0x7FFFFFFF;
+}
+__host__ __device__ inline float ordered_to_float(int i) {
+    int b = i >= 0 ? i : i ^ 0x7FFFFFFF;
+    union {
+        int i;
+        float f;
+    } u;
+    u.i = b;
+    return u.f;
+}
+
+// ---------------------------------------------------------------------------
+// Device control block: counters and scalars that decide the data-dependent
+// control flow of a cycle without a host round trip.
+// ---------------------------------------------------------------------------
+enum ListId { L_ACT = 0, L_T1, L_T2, L_FD, L_UNF, L_STK, O_SLOTS, O_FREE, O_PEAKS, kNumLists };
+
+struct Ctl {
+    int k;  // cycles completed
+    int count[kNumLists];
+    int fmax_ord;  // ordered-int image of f_max
+    int n_stuck, K_lost, n_modes, n_active;
+    int reseed_kind;  // 0 none, 1 RM, 2 GR, 3 deactivate
+    int gr_disabled, gr_fail, gr_used_last, gr_prev_modes;
+    int ls_fail;
+    int evals;
+    float f_max, sigma, alpha_c, alpha_a;
+};
+
+// Per-cycle record kept on the device, copied out on request.
+struct CycleRecord {
+    int k;
+    float f_max;
+    int n_stuck, K_lost, n_modes, reseed_kind, n_free, n_unfrozen, n_active;
+    float sigma, alpha_c, alpha_a;
+    int ls_fail, evals;
+};
+
+// Status bytes written by the line-search epilogue.
+constexpr uint8_t kStAccept = 0x80;  // | accepted trial index
+constexpr uint8_t kStFail = 0x40;
+
+// Decision-trace codes (one byte per sample and L-BFGS iteration).
+constexpr uint8_t kTrNone = 0xFF;
+constexpr uint8_t kTrFail = 0x0F;
+constexpr uint8_t kTrStored = 0x10;
+constexpr uint8_t kTrConv = 0x20;
+constexpr uint8_t kTrReset = 0x40;
+
+// Everything a kernel needs, passed by value.
+struct Dev {
+    // problem
+    int d, DP, K, family;
+    float nu, nu_plus_d;
+    const float *Pfrag;  // [K][DP/4][64][DP/16] MFMA A-operand fragments of the precision matrices
+    const float *muB;    // [K][4][DP/4]  centre coordinates in B-operand lane order
+    const float *muC;    // [K][4][DP/4]  centre coordinates in accumulator lane order
+    const float *logc2;  // [K] log2 of weight times normaliser
+    const float *lo, *hi;
+    // schedule and hyperparameters
+    int N, m, n_osc, n_conv, n_anti, n_cloud, M, ls_max, grad_mode;
+    float eps_grad, eps_dup, log_delta, momentum, alpha, sigma_cfg, sigma_c, fd_h, ls_c1, curv_eps;
+    uint32_t key0, key1, phase_mask;
+    // population state
+    float *X, *F, *G, *V, *Xprev, *Gprev, *Pd, *Gh, *Gp, *ginf;
+    uint8_t *stuck, *active, *conv, *removed, *stuck_pre, *status, *reset, *trace;
+    float *S, *Y, *rho;
+    int *head, *cnt;
+    int *lists;  // kNumLists x N
+    Ctl *ctl;
+    CycleRecord *records;  // n_osc entries
+    double *part;          // reduction partials
+    int n_part_blocks;
+};
+
+__device__ __forceinline__ int *list_ptr(const Dev &D, int id) { return D.lists + (size_t)id * D.N; }
+
+}  // namespace chisao

@@ -1,0 +1,461 @@
+// Batched mixture objective and adjoint gradient on FP32 MFMA (gfx950).
+//
+// For a point x and component k the kernel forms delta = x - mu_k (centring
+// before the product keeps FP32 cancellation out of the contraction) and
+// u_k = P_k delta with P_k the precision matrix.  Then
+//   q_k = delta . u_k,   l_k = log c_k - q_k / 2           (Gaussian)
+//                        l_k = log c_k - (nu+d)/2 log1p(q_k/nu)  (Student-t)
+//   f = log sum_k exp(l_k),   grad f = -sum_k r_k s_k u_k,
+// with r = softmax(l) and s_k = 1 (Gaussian) or (nu+d)/(nu+q_k) (Student-t).
+// The same contraction therefore yields the value and its reverse-mode
+// gradient: 2 K d^2 MFMA flops per point whether or not the gradient is kept.
+//
+// Work layout: one wave per workgroup, 32 points per wave in two 16-point
+// blocks.  v_mfma_f32_16x16x4f32 computes U^T (DP x 16) = P (DP x DP) *
+// Delta^T (DP x 16): lane l supplies P[16mb + l%16][4ks + l/16] (A operand)
+// and delta[point l%16][4ks + l/16] (B operand), and receives
+// u[point l%16][16mb + 4(l/16) + r], r = 0..3.  Components are streamed; the
+// log-sum-exp runs online in base 2 (one rescale per wave only when some
+// lane's running maximum moves).
+#include <math.h>
+
+#include "kernels.h"
+
+namespace chisao {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+constexpr int NB = 2;    // 16-point blocks per wave
+constexpr int PPW = 32;  // points per wave
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kLn2 = 0.6931471805599453f;
+
+template <int MB>
+__device__ __forceinline__ void load_frag(const float *p, float out[MB]) {
+    if constexpr (MB == 4) {
+        f32x4 v = *reinterpret_cast<const f32x4 *>(p);
+        out[0] = v[0]; out[1] = v[1]; out[2] = v[2]; out[3] = v[3];
+    } else if constexpr (MB == 2) {
+        f32x2 v = *reinterpret_cast<const f32x2 *>(p);
+        out[0] = v[0]; out[1] = v[1];
+    } else {
+        out[0] = *p;
+    }
+}
+
+template <int DP, int FAM, bool GRAD, int CENTER, bool FD>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void eval_kernel(EvalArgs a) {
+    constexpr int KS = DP / 4;
+    constexpr int MB = DP / 16;
+    constexpr int LD = DP + 1;  // padded row: conflict-free column reads
+    __shared__ float s_pts[PPW * LD];
+    __shared__ float s_g[GRAD ? PPW * LD : 1];
+    __shared__ float s_f[PPW];
+    __shared__ float s_den[PPW];
+    __shared__ int s_s[PPW];    // sample per point, -1 when the lane is idle
+    __shared__ int s_c[PPW];    // centre index within the job
+    __shared__ int s_st[PPW];   // stencil index within the centre
+    __shared__ int s_pass[PPW];
+    __shared__ int s_acc[PPW];
+
+    const Dev &D = a.D;
+    const int lane = threadIdx.x;
+    const int g = lane >> 4, n = lane & 15;
+    const int d = D.d;
+    const int count = a.count_ptr ? *a.count_ptr : a.n_jobs;
+    const int Vs = FD ? 2 * d : 1;
+    const int V = a.Vc * Vs;
+    int jpw, wpj;
+    long n_tiles;
+    if (V <= PPW) {
+        jpw = PPW / V;
+        wpj = 1;
+        n_tiles = (count + jpw - 1) / jpw;
+    } else {
+        jpw = 1;
+        wpj = (V + PPW - 1) / PPW;
+        n_tiles = (long)count * wpj;
+    }
+    const uint32_t kcyc = (uint32_t)D.ctl->k + 1u;
+    const float sigma = (CENTER == kProbe) ? D.ctl->sigma : 0.0f;
+
+    for (long tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        // ---- point metadata ------------------------------------------------
+        if (lane < PPW) {
+            const int p = lane;
+            int job, v;
+            bool valid;
+            if (V <= PPW) {
+                job = (int)(tile * jpw) + p / V;
+                v = p % V;
+                valid = (p < jpw * V) && job < count;
+            } else {
+                job = (int)(tile / wpj);
+                v = (int)(tile % wpj) * PPW + p;
+                valid = v < V;
+            }
+            s_s[p] = valid ? (a.list ? a.list[job] : job) : -1;
+            s_c[p] = v / Vs;
+            s_st[p] = v % Vs;
+            s_den[p] = 1.0f;
+        }
+        __syncthreads();
+        // ---- generate the points (zero padded to DP) -----------------------
+        for (int e = lane; e < PPW * KS; e += kWave) {
+            const int p = e / KS, blk = e % KS, c0 = 4 * blk;
+            const int s = s_s[p];
+            float x[4] = {0.f, 0.f, 0.f, 0.f};
+            if (s >= 0) {
+                const int ci = s_c[p];
+                float z[4] = {0.f, 0.f, 0.f, 0.f};
+                if constexpr (CENTER == kProbe) {
+                    const uint32_t pair = (uint32_t)(ci >> 1);
+                    uint4 o = philox((uint32_t)s, kcyc, (kHLC << 24) | ((uint32_t)a.step << 16) | pair,
+                                     (uint32_t)blk, D.key0, D.key1);
+                    box_muller4(o, z);
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int c = c0 + q;
+                    if (c < d) {
+                        float xv = a.X[(size_t)s * d + c];
+                        if constexpr (CENTER == kTrial) {
+                            const float t = ldexpf(1.0f, -(a.r0 + ci));
+                            xv = fminf(fmaxf(xv + t * D.Pd[(size_t)s * d + c], D.lo[c]), D.hi[c]);
+                        } else if constexpr (CENTER == kProbe) {
+                            const float sgn = (ci & 1) ? -1.0f : 1.0f;
+                            xv = xv + sigma * sgn * z[q];
+                        }
+                        x[q] = xv;
+                    }
+                }
+                if constexpr (FD) {
+                    const int st = s_st[p];
+                    const int cs = st >> 1;
+                    if (cs >= c0 && cs < c0 + 4) {
+                        const float xc = x[cs - c0];
+                        const float h = D.fd_h > 0.0f ? D.fd_h : ldexpf(fmaxf(1.0f, fabsf(xc)), -8);
+                        const float xp = xc + h, xm = xc - h;
+                        x[cs - c0] = (st & 1) ? xm : xp;
+                        s_den[p] = xp - xm;
+                    }
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) s_pts[p * LD + c0 + q] = x[q];
+        }
+        __syncthreads();
+        // ---- operand registers ---------------------------------------------
+        float xB[NB][KS], xC[NB][KS];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            const float *row = s_pts + (nb * 16 + n) * LD;
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) xB[nb][ks] = row[4 * ks + g];
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) xC[nb][mb * 4 + r] = row[16 * mb + 4 * g + r];
+        }
+        float mrun[NB], srun[NB];
+        float gacc[NB][GRAD ? KS : 1];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            mrun[nb] = -INFINITY;
+            srun[nb] = 0.0f;
+            if constexpr (GRAD)
+#pragma unroll
+                for (int i = 0; i < KS; ++i) gacc[nb][i] = 0.0f;
+        }
+        // ---- stream the components -----------------------------------------
+        for (int k = 0; k < D.K; ++k) {
+            const float *pf = D.Pfrag + (size_t)k * KS * kWave * MB + lane * MB;
+            const float *mb_p = D.muB + ((size_t)k * 4 + g) * KS;
+            const float *mc_p = D.muC + ((size_t)k * 4 + g) * KS;
+            float muB[KS], muC[KS];
+#pragma unroll
+            for (int i = 0; i < KS; i += 4) {
+                f32x4 vb = *reinterpret_cast<const f32x4 *>(mb_p + i);
+                f32x4 vc = *reinterpret_cast<const f32x4 *>(mc_p + i);
+                muB[i] = vb[0]; muB[i + 1] = vb[1]; muB[i + 2] = vb[2]; muB[i + 3] = vb[3];
+                muC[i] = vc[0]; muC[i + 1] = vc[1]; muC[i + 2] = vc[2]; muC[i + 3] = vc[3];
+            }
+            f32x4 acc[NB][MB];
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+                for (int mb = 0; mb < MB; ++mb) acc[nb][mb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                float pa[MB];
+                load_frag<MB>(pf + (size_t)ks * kWave * MB, pa);
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) {
+                    const float b = xB[nb][ks] - muB[ks];
+#pragma unroll
+                    for (int mb = 0; mb < MB; ++mb)
+                        acc[nb][mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(pa[mb], b, acc[nb][mb], 0, 0, 0);
+                }
+            }
+            const float lc2 = D.logc2[k];
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                float q = 0.0f;
+#pragma unroll
+                for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) q = fmaf(xC[nb][mb * 4 + r] - muC[mb * 4 + r], acc[nb][mb][r], q);
+                q += __shfl_xor(q, 16, kWave);
+                q += __shfl_xor(q, 32, kWave);
+                float l2, w = 1.0f;
+                if constexpr (FAM == 0) {
+                    l2 = lc2 - q * (0.5f * kLog2e);
+                } else {
+                    l2 = lc2 - (0.5f * D.nu_plus_d * kLog2e) * log1pf(q / D.nu);
+                    w = D.nu_plus_d / (D.nu + q);
+                }
+                const float mnew = fmaxf(mrun[nb], l2);
+                const float sc = __builtin_amdgcn_exp2f(mrun[nb] - mnew);
+                const float pk = __builtin_amdgcn_exp2f(l2 - mnew);
+                const bool moved = mnew > mrun[nb];
+                srun[nb] = fmaf(srun[nb], sc, pk);
+                mrun[nb] = mnew;
+                if constexpr (GRAD) {
+                    if (__any(moved)) {
+#pragma unroll
+                        for (int i = 0; i < KS; ++i) gacc[nb][i] *= sc;
+                    }
+                    const float pw = pk * w;
+#pragma unroll
+                    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+                            gacc[nb][mb * 4 + r] = fmaf(pw, acc[nb][mb][r], gacc[nb][mb * 4 + r]);
+                }
+            }
+        }
+        // ---- results to LDS ------------------------------------------------
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            const int p = nb * 16 + n;
+            const float f = (mrun[nb] + __log2f(srun[nb])) * kLn2;
+            if (g == 0) s_f[p] = f;
+            if constexpr (GRAD) {
+                const float inv = -1.0f / srun[nb];
+#pragma unroll
+                for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) s_g[p * LD + 16 * mb + 4 * g + r] = gacc[nb][mb * 4 + r] * inv;
+            }
+        }
+        __syncthreads();
+        if (lane == 0) {
+            int nv = 0;
+            for (int p = 0; p < PPW; ++p) nv += (s_s[p] >= 0);
+            atomicAdd(&D.ctl->evals, nv);
+        }
+        // ---- epilogues -----------------------------------------------------
+        if constexpr (CENTER == kDirect && !FD) {
+            if (lane < PPW && s_s[lane] >= 0 && a.F_out) a.F_out[s_s[lane]] = s_f[lane];
+            if constexpr (GRAD) {
+                if (a.G_out)
+                    for (int e = lane; e < PPW * d; e += kWave) {
+                        const int p = e / d, c = e % d, s = s_s[p];
+                        if (s >= 0) a.G_out[(size_t)s * d + c] = s_g[p * LD + c];
+                    }
+            }
+        } else if constexpr (FD) {
+            if (lane < PPW) {
+                const int p = lane, s = s_s[p], st = s_st[p];
+                if (s >= 0 && (st & 1) == 0) {
+                    const float gv = (s_f[p] - s_f[p + 1]) / s_den[p];
+                    const int c = st >> 1;
+                    if constexpr (CENTER == kDirect) a.G_out[(size_t)s * d + c] = gv;
+                    else D.Gp[((size_t)s * D.M + s_c[p]) * d + c] = gv;
+                }
+            }
+        } else if constexpr (CENTER == kProbe) {
+            // mean over the job's probes, summed in probe order
+            const float invM = 1.0f / (float)a.Vc;
+            for (int e = lane; e < jpw * d; e += kWave) {
+                const int j = e / d, c = e % d, p0 = j * a.Vc, s = s_s[p0];
+                if (s >= 0) {
+                    float acc = 0.0f;
+                    for (int mm = 0; mm < a.Vc; ++mm) acc += s_g[(p0 + mm) * LD + c];
+                    D.Gh[(size_t)s * d + c] = acc * invM;
+                }
+            }
+        } else if constexpr (CENTER == kTrial) {
+            // Armijo margins f_tr - f - c1 g.(x_tr - x), two lanes per point
+            {
+                const int p = lane >> 1, h = lane & 1, s = s_s[p];
+                float dot = 0.0f;
+                if (s >= 0)
+                    for (int c = h; c < d; c += 2)
+                        dot += D.G[(size_t)s * d + c] * (s_pts[p * LD + c] - D.X[(size_t)s * d + c]);
+                dot += __shfl_xor(dot, 1, kWave);
+                if (h == 0) s_pass[p] = (s >= 0) && (s_f[p] - D.F[s] - D.ls_c1 * dot >= 0.0f);
+            }
+            __syncthreads();
+            if (lane < jpw) {
+                int r = -1;
+                const int p0 = lane * a.Vc;
+                if (s_s[p0] >= 0)
+                    for (int i = 0; i < a.Vc; ++i)
+                        if (s_pass[p0 + i]) { r = i; break; }
+                s_acc[lane] = r;
+            }
+            __syncthreads();
+            for (int e = lane; e < jpw * d; e += kWave) {
+                const int j = e / d, c = e % d, p0 = j * a.Vc, s = s_s[p0];
+                if (s >= 0 && s_acc[j] >= 0) {
+                    const int pa = p0 + s_acc[j];
+                    const size_t o = (size_t)s * d + c;
+                    D.Xprev[o] = D.X[o];
+                    D.X[o] = s_pts[pa * LD + c];
+                    D.Gprev[o] = D.G[o];
+                    if constexpr (GRAD) D.G[o] = s_g[pa * LD + c];
+                }
+            }
+            if (lane < jpw) {
+                const int p0 = lane * a.Vc, s = s_s[p0];
+                if (s >= 0) {
+                    const int r = s_acc[lane];
+                    if (r >= 0) {
+                        D.F[s] = s_f[p0 + r];
+                        D.status[s] = (uint8_t)(kStAccept | (a.r0 + r));
+                        if constexpr (!GRAD) {
+                            const int slot = atomicAdd(&D.ctl->count[L_FD], 1);
+                            list_ptr(D, L_FD)[slot] = s;
+                        }
+                    } else if (a.trial_next >= 0) {
+                        const int slot = atomicAdd(&D.ctl->count[a.trial_next], 1);
+                        list_ptr(D, a.trial_next)[slot] = s;
+                    } else {
+                        D.status[s] = kStFail;
+                        atomicAdd(&D.ctl->ls_fail, 1);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Dispatch
+// ---------------------------------------------------------------------------
+template <int DP, int FAM>
+static hipError_t dispatch_modes(const EvalArgs &a, int center, bool fd, bool grad, dim3 grid, hipStream_t st) {
+    const dim3 block(kWave);
+#define CHISAO_GO(C, G, F) hipLaunchKernelGGL((eval_kernel<DP, FAM, G, C, F>), grid, block, 0, st, a)
+    if (center == kDirect) {
+        if (fd) CHISAO_GO(kDirect, false, true);
+        else if (grad) CHISAO_GO(kDirect, true, false);
+        else CHISAO_GO(kDirect, false, false);
+    } else if (center == kTrial) {
+        if (grad) CHISAO_GO(kTrial, true, false);
+        else CHISAO_GO(kTrial, false, false);
+    } else {
+        if (fd) CHISAO_GO(kProbe, false, true);
+        else CHISAO_GO(kProbe, true, false);
+    }
+#undef CHISAO_GO
+    return hipGetLastError();
+}
+
+hipError_t launch_eval(const EvalArgs &a, int center, bool fd, bool grad, hipStream_t st) {
+    if (a.n_jobs <= 0) return hipSuccess;
+    const int Vs = fd ? 2 * a.D.d : 1;
+    const long V = (long)a.Vc * Vs;
+    long tiles = V <= PPW ? (a.n_jobs + (PPW / V) - 1) / (PPW / V) : (long)a.n_jobs * ((V + PPW - 1) / PPW);
+    const long cap = 8192;
+    dim3 grid((unsigned)(tiles < cap ? tiles : cap));
+    const int fam = a.D.family;
+    switch (a.D.DP) {
+        case 16: return fam ? dispatch_modes<16, 1>(a, center, fd, grad, grid, st)
+                            : dispatch_modes<16, 0>(a, center, fd, grad, grid, st);
+        case 32: return fam ? dispatch_modes<32, 1>(a, center, fd, grad, grid, st)
+                            : dispatch_modes<32, 0>(a, center, fd, grad, grid, st);
+        case 64: return fam ? dispatch_modes<64, 1>(a, center, fd, grad, grid, st)
+                            : dispatch_modes<64, 0>(a, center, fd, grad, grid, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Per-component constants.  One workgroup per component: float64 Cholesky of
+// the precision matrix for log|P_k| (setup only), then the MFMA fragment
+// layouts.  bad[0] is set when a matrix is not positive definite.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void prepare_kernel(int family, int d, int DP, int K, float nu, const float *log_w,
+                                                     const float *mu, const float *prec, float *logc2, float *Pfrag,
+                                                     float *muB, float *muC, int *bad) {
+    const int k = blockIdx.x;
+    const int lane = threadIdx.x;
+    __shared__ double L[64 * 64];
+    __shared__ double diag_log[64];
+    const float *A = prec + (size_t)k * d * d;
+    for (int e = lane; e < d * d; e += 64) L[e] = (double)A[e];
+    __syncthreads();
+    // right-looking Cholesky, one column at a time
+    for (int j = 0; j < d; ++j) {
+        if (lane == 0) {
+            double v = L[j * d + j];
+            if (!(v > 0.0)) {
+                atomicExch(bad, 1);
+                v = 1.0;
+            }
+            L[j * d + j] = sqrt(v);
+            diag_log[j] = log(L[j * d + j]);
+        }
+        __syncthreads();
+        for (int i = j + 1 + lane; i < d; i += 64) L[i * d + j] /= L[j * d + j];
+        __syncthreads();
+        for (int e = lane; e < (d - j - 1) * (d - j - 1); e += 64) {
+            const int i = j + 1 + e / (d - j - 1), c = j + 1 + e % (d - j - 1);
+            if (c <= i) L[i * d + c] -= L[i * d + j] * L[c * d + j];
+        }
+        __syncthreads();
+    }
+    if (lane == 0) {
+        double logdet = 0.0;
+        for (int j = 0; j < d; ++j) logdet += 2.0 * diag_log[j];
+        const double log_2pi = 1.8378770664093454835606594728112;
+        double c;
+        if (family == 0) {
+            c = -0.5 * d * log_2pi + 0.5 * logdet;
+        } else {
+            c = lgamma(0.5 * ((double)nu + d)) - lgamma(0.5 * (double)nu) - 0.5 * d * log((double)nu * M_PI) +
+                0.5 * logdet;
+        }
+        logc2[k] = (float)(((double)log_w[k] + c) * 1.4426950408889634);
+    }
+    // fragments: Pfrag[k][ks][lane][mb] = P[16 mb + lane%16][4 ks + lane/16]
+    const int KS = DP / 4, MB = DP / 16;
+    for (int ks = 0; ks < KS; ++ks)
+        for (int mb = 0; mb < MB; ++mb) {
+            const int row = 16 * mb + (lane & 15), col = 4 * ks + (lane >> 4);
+            const float v = (row < d && col < d) ? A[row * d + col] : 0.0f;
+            Pfrag[(((size_t)k * KS + ks) * 64 + lane) * MB + mb] = v;
+        }
+    // centres: muB[k][g][ks] = mu[4 ks + g]; muC[k][g][4 mb + r] = mu[16 mb + 4 g + r]
+    if (lane < 4 * KS) {
+        const int gg = lane / KS, i = lane % KS;
+        const int cb = 4 * i + gg;
+        const int cc = 16 * (i / 4) + 4 * gg + (i % 4);
+        muB[((size_t)k * 4 + gg) * KS + i] = cb < d ? mu[(size_t)k * d + cb] : 0.0f;
+        muC[((size_t)k * 4 + gg) * KS + i] = cc < d ? mu[(size_t)k * d + cc] : 0.0f;
+    }
+}
+
+hipError_t launch_prepare(int family, int d, int DP, int K, float nu, const float *log_w, const float *mu,
+                          const float *prec, float *logc2, float *Pfrag, float *muB, float *muC, int *bad,
+                          hipStream_t st) {
+    hipLaunchKernelGGL(prepare_kernel, dim3(K), dim3(64), 0, st, family, d, DP, K, nu, log_w, mu, prec, logc2,
+                       Pfrag, muB, muC, bad);
+    return hipGetLastError();
+}
+
+}  // namespace chisao

@@ -1,0 +1,76 @@
+"""Host-side checks of the C ABI: the library loads and exports every symbol
+the header declares, and the ctypes layouts match the header's structs."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "chisao.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(chisao_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared_functions()
+    for required in ("chisao_init", "chisao_cycle", "chisao_modes"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2606_26164_amd import _lib
+
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libchisao.so is not built; run `python -m paper_2606_26164_amd.build`")
+    lib = C.CDLL(_lib.LIB_PATH)
+    for name in _declared_functions():
+        assert hasattr(lib, name), name
+    assert set(_declared_functions()) == set(_lib.EXPORTS)
+
+
+def test_ctypes_struct_layouts_match_header():
+    """Compile a tiny C program that prints sizeof/offsetof of the header's
+    structs and compare with the ctypes declarations."""
+    import subprocess
+    import tempfile
+
+    from paper_2606_26164_amd import _lib
+
+    src = r'''
+#include <stddef.h>
+#include <stdio.h>
+#include "chisao.h"
+#define P(T, f) printf(#T " " #f " %zu\n", offsetof(T, f));
+int main(void) {
+  printf("chisao_problem size %zu\n", sizeof(chisao_problem));
+  printf("chisao_config size %zu\n", sizeof(chisao_config));
+  printf("chisao_cycle_stats size %zu\n", sizeof(chisao_cycle_stats));
+  printf("chisao_state size %zu\n", sizeof(chisao_state));
+  P(chisao_problem, noise_sigma) P(chisao_config, seed) P(chisao_config, problem_id)
+  P(chisao_config, phase_mask) P(chisao_cycle_stats, evals) P(chisao_state, k) P(chisao_state, gr_prev_modes)
+  return 0;
+}
+'''
+    with tempfile.TemporaryDirectory() as td:
+        c = os.path.join(td, "l.c")
+        open(c, "w").write(src)
+        exe = os.path.join(td, "l")
+        subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
+        out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for ln in out:
+        if ln.strip():
+            t, f, v = ln.split()
+            got[(t, f)] = int(v)
+    m = {"chisao_problem": _lib.Problem, "chisao_config": _lib.Config, "chisao_cycle_stats": _lib.CycleStats,
+         "chisao_state": _lib.State}
+    for (t, f), v in got.items():
+        cls = m[t]
+        if f == "size":
+            assert C.sizeof(cls) == v, (t, C.sizeof(cls), v)
+        else:
+            assert getattr(cls, f).offset == v, (t, f)

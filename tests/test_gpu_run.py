@@ -1,0 +1,128 @@
+"""End-to-end GPU runs through the C ABI: recovered mode sets against the
+FP64 oracle, error handling of the boundary, and reproducibility."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+def _match(A, B, tol=1e-3):
+    """One-to-one L-infinity matching within tol (clusters are far apart)."""
+    if len(A) != len(B):
+        return False
+    used = set()
+    for a in A:
+        dist = np.abs(B - a).max(1) if len(B) else np.array([])
+        j = int(np.argmin(dist)) if len(dist) else -1
+        if j < 0 or dist[j] >= tol or j in used:
+            return False
+        used.add(j)
+    return True
+
+
+def test_config1_mode_set_matches_oracle():
+    from paper_2606_26164_amd.api import Optimizer
+
+    prob, cfg, x0 = W.config1()
+    run = O.OracleRun(prob, cfg, x0)  # the configuration's own FP64 finite-difference run
+    run.run()
+    Xo, Fo, _ = run.modes()
+    # FP32 on the GPU: adjoint and central differences, threshold at the FP32 floor
+    for mode in (1, 0):
+        gcfg = cfg.with_(grad_mode=mode, eps_grad=1e-4, fd_h=0.0)
+        with Optimizer(prob, gcfg, x0) as opt:
+            stats = opt.cycle(cfg.n_osc, stats=True)
+            ms = opt.modes()
+        assert stats[-1]["k"] == cfg.n_osc
+        assert _match(ms.X.astype(np.float64), Xo), (mode, ms.X, Xo)
+        np.testing.assert_allclose(ms.F, Fo, rtol=1e-5, atol=1e-5)
+
+
+def test_cycle_past_schedule_is_rejected_and_state_kept():
+    from paper_2606_26164_amd import _lib as L
+    from paper_2606_26164_amd.api import Optimizer
+
+    prob, cfg, x0 = W.config1(N=32)
+    cfg = cfg.with_(n_osc=2, grad_mode=1, eps_grad=1e-4)
+    with Optimizer(prob, cfg, x0) as opt:
+        opt.cycle(2)
+        before = opt.get_state()["X"].copy()
+        with pytest.raises(L.ChisaoError) as ei:
+            opt.cycle(1)
+        assert ei.value.code == L.E_STATE
+        np.testing.assert_array_equal(opt.get_state()["X"], before)
+
+
+def test_modes_capacity_error_reports_count():
+    import ctypes as C
+
+    from paper_2606_26164_amd import _lib as L
+    from paper_2606_26164_amd.api import Optimizer
+
+    prob, cfg, x0 = W.config1(N=64)
+    cfg = cfg.with_(n_osc=3, grad_mode=1, eps_grad=1e-4)
+    with Optimizer(prob, cfg, x0) as opt:
+        opt.cycle(3)
+        n = C.c_int(-1)
+        X = np.zeros((1, 2), np.float32)
+        rc = opt.lib.chisao_modes(opt.h, 0, X.ctypes.data, None, 0, C.byref(n))
+        assert rc == L.E_RANGE and n.value == len(opt.modes().X) and n.value >= 1
+        assert np.all(X == 0)
+
+
+def test_invalid_problems_are_rejected():
+    from paper_2606_26164_amd import _lib as L
+    from paper_2606_26164_amd.api import Optimizer
+
+    prob, cfg, x0 = W.config1(N=16)
+    bad = W.mixture_problem(0, 2, 4, 5.0, isotropic_var=0.25, dirichlet=None)
+    bad.prec = bad.prec.copy()
+    bad.prec[0, 0, 1] += 0.5  # not symmetric
+    with pytest.raises(L.ChisaoError) as ei:
+        Optimizer(bad, cfg, x0)
+    assert ei.value.code == L.E_INVAL
+    bad2 = W.mixture_problem(0, 2, 4, 5.0, isotropic_var=0.25, dirichlet=None)
+    bad2.prec = bad2.prec.copy()
+    bad2.prec[1] = -bad2.prec[1]  # symmetric, not positive definite
+    with pytest.raises(L.ChisaoError) as ei:
+        Optimizer(bad2, cfg, x0)
+    assert ei.value.code == L.E_INVAL
+    with pytest.raises(L.ChisaoError):
+        Optimizer(prob, cfg.with_(M=33), x0)
+    outside = x0.copy()
+    outside[3, 0] = 100.0
+    with pytest.raises(L.ChisaoError):
+        Optimizer(prob, cfg, outside)
+
+
+def test_same_seed_same_state_bitwise():
+    from paper_2606_26164_amd.api import Optimizer
+
+    prob, cfg, x0 = W.config3(N=256, n_osc=3)
+    outs = []
+    for _ in range(2):
+        with Optimizer(prob, cfg, x0) as opt:
+            opt.cycle(2)
+            outs.append(opt.get_state())
+    for key in ("X", "F", "G", "stuck", "active", "trace"):
+        np.testing.assert_array_equal(outs[0][key], outs[1][key], err_msg=key)
+
+
+def test_config3_shape_runs_every_phase():
+    """d=64, K=128 at a small population: every phase executes and the state
+    stays inside the box; sample counts are consistent."""
+    from paper_2606_26164_amd.api import Optimizer
+
+    prob, cfg, x0 = W.config3(N=512, n_osc=4)
+    with Optimizer(prob, cfg, x0) as opt:
+        stats = opt.cycle(4, stats=True)
+        st = opt.get_state()
+    X = st["X"]
+    assert np.all(X >= prob.lo) and np.all(X <= prob.hi)
+    for s in stats:
+        assert s["n_modes"] + s["K_lost"] == s["n_stuck"]
+        assert s["sigma"] == pytest.approx(0.1)
+    assert stats[0]["evals"] > 512 * 18
