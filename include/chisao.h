@@ -123,6 +123,14 @@ typedef struct {
                            bit 4 pair stored; bit 5 converged; bit 6 direction reset */
     int32_t k;          /* cycles completed */
     int32_t gr_disabled, gr_fail, gr_used_last, gr_prev_modes; /* Golden Rooster generation state */
+    /* L-BFGS history of the last Phase 1 (get only): pairs (s, y) for F = -f
+       in a ring of m slots per sample, newest in slot head, cnt pairs valid */
+    float *S;           /* [N*m*d] */
+    float *Y;           /* [N*m*d] */
+    float *rho;         /* [N*m] 1 / s'y */
+    int32_t *head;      /* [N] */
+    int32_t *cnt;       /* [N] */
+    uint8_t *conv;      /* [N] converged flags of the last Phase 1 */
 } chisao_state;
 
 typedef struct chisao_ctx *chisao_handle;

@@ -88,6 +88,7 @@ typedef struct {
     int64_t n_decisions, n_borderline, n_hard;
     double worst_hard;
     int32_t first_hard_sample, first_hard_iter, first_hard_kind;
+    int64_t border_by_kind[8], hard_by_kind[8];
 } orc_replay;
 
 /* ------------------------------------------------------------------------ */
@@ -387,15 +388,18 @@ typedef struct {
     int32_t n_dec, n_border, n_hard;
     double worst;
     int32_t hard_iter, hard_kind;
+    int32_t border_kind[8], hard_kind_n[8];
 } sample_replay_t;
 
 static void note_disagreement(sample_replay_t *sr, int borderline, double margin, int iter, int kind)
 {
     if (borderline) {
         sr->n_border++;
+        sr->border_kind[kind & 7]++;
     } else {
         if (sr->n_hard == 0) { sr->hard_iter = iter; sr->hard_kind = kind; }
         sr->n_hard++;
+        sr->hard_kind_n[kind & 7]++;
         if (fabs(margin) > sr->worst) sr->worst = fabs(margin);
     }
 }
@@ -408,6 +412,10 @@ static void fold_replay(orc_replay *R, const sample_replay_t *sr, int N)
     for (int i = 0; i < N; ++i) {
         R->n_decisions += sr[i].n_dec;
         R->n_borderline += sr[i].n_border;
+        for (int q = 0; q < 8; ++q) {
+            R->border_by_kind[q] += sr[i].border_kind[q];
+            R->hard_by_kind[q] += sr[i].hard_kind_n[q];
+        }
         if (sr[i].n_hard > 0) {
             if (R->n_hard == 0) {
                 R->first_hard_sample = i;
@@ -462,6 +470,10 @@ static void lbfgs_iteration(const orc_problem *P, const double *logc, const orc_
         if (sc->margins[t] >= 0.0) { own = t; break; }
     }
     int use = own;
+    if (forced && *forced == TR_NONE) {
+        sr->n_dec++;
+        note_disagreement(sr, 0, 1.0, iter, KIND_LS);
+    }
     if (forced) {
         int gpu = (*forced == TR_NONE) ? -1 : (*forced & TR_LS_MASK);
         sr->n_dec++;
@@ -587,6 +599,41 @@ int orc_phase_converge(const orc_problem *P, const double *logc, const orc_confi
             if (trace) trace[i] = code;
         }
         for (int it = 1; it <= C->n_conv; ++it) {
+#pragma omp for schedule(dynamic, 2)
+            for (int i = 0; i < N; ++i) {
+                uint8_t code = TR_NONE;
+                if (S->active[i] && !S->conv[i] && !err)
+                    lbfgs_iteration(P, logc, C, S, i, it, &sc, R, &sr[i], &code);
+                if (trace) trace[(size_t)it * N + i] = code;
+            }
+        }
+        scratch_free(&sc);
+    }
+    fold_replay(R, sr, N);
+    free(sr);
+    return err ? ORC_ENOMEM : ORC_OK;
+}
+
+/* Continue Phase 1 from the current state: iterations first..first+n-1 for
+ * active samples not yet converged, with the stored histories (no release, no
+ * initial evaluation).  Trace rows are indexed by iteration number. */
+int orc_lbfgs_iterate(const orc_problem *P, const double *logc, const orc_config *C, orc_state *S, int first, int n,
+                      orc_replay *R)
+{
+    int N = C->N;
+    if (first < 1 || first + n - 1 > C->n_conv) return ORC_EINVAL;
+    sample_replay_t *sr = (sample_replay_t *)calloc((size_t)N, sizeof(sample_replay_t));
+    if (!sr) return ORC_ENOMEM;
+    uint8_t *trace = (R && R->trace_out) ? R->trace_out : NULL;
+    int err = 0;
+#pragma omp parallel
+    {
+        scratch_t sc;
+        if (scratch_alloc(&sc, P, C)) {
+#pragma omp atomic write
+            err = 1;
+        }
+        for (int it = first; it < first + n; ++it) {
 #pragma omp for schedule(dynamic, 2)
             for (int i = 0; i < N; ++i) {
                 uint8_t code = TR_NONE;

@@ -70,7 +70,7 @@ class _Replay(C.Structure):
                 ("tol_curv", C.c_double), ("tol_dist", C.c_double), ("n_decisions", C.c_int64),
                 ("n_borderline", C.c_int64), ("n_hard", C.c_int64), ("worst_hard", C.c_double),
                 ("first_hard_sample", C.c_int32), ("first_hard_iter", C.c_int32),
-                ("first_hard_kind", C.c_int32)]
+                ("first_hard_kind", C.c_int32), ("border_by_kind", C.c_int64 * 8), ("hard_by_kind", C.c_int64 * 8)]
 
 
 _lib = None
@@ -93,6 +93,8 @@ def lib():
         L.orc_householder_q.argtypes = [C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]
         for name in ("orc_phase_converge", "orc_cycle"):
             getattr(L, name).argtypes = [P(_Problem), C.c_void_p, P(_Config), P(_State), P(_Replay)]
+        L.orc_lbfgs_iterate.argtypes = [P(_Problem), C.c_void_p, P(_Config), P(_State), C.c_int, C.c_int,
+                                        P(_Replay)]
         L.orc_phase_stick.argtypes = [P(_Problem), P(_Config), P(_State), P(_Replay)]
         L.orc_phase_dedup.argtypes = [P(_Problem), P(_Config), P(_State), P(_Replay)]
         L.orc_phase_reseed.argtypes = [P(_Problem), P(_Config), P(_State)]
@@ -173,6 +175,9 @@ class ReplayReport:
     first_hard_sample: int
     first_hard_iter: int
     first_hard_kind: int
+    # indices: 1 line search, 2 curvature store, 3 convergence, 4 stick, 5 dedup
+    border_by_kind: tuple = ()
+    hard_by_kind: tuple = ()
 
 
 class OracleRun:
@@ -222,12 +227,13 @@ class OracleRun:
         self._keep = [np.ascontiguousarray(a, dtype=np.uint8) if a is not None else None
                       for a in (trace_in, stuck_in, removed_in)]
         return _Replay(_ptr(self.trace), _ptr(self._keep[0]), _ptr(self._keep[1]), _ptr(self._keep[2]), tol_f,
-                       tol_g, tol_curv, tol_dist, 0, 0, 0, 0.0, -1, -1, 0)
+                       tol_g, tol_curv, tol_dist, 0, 0, 0, 0.0, -1, -1, 0)  # per-kind counters start at zero
 
     @staticmethod
     def _report(r: _Replay) -> ReplayReport:
         return ReplayReport(int(r.n_decisions), int(r.n_borderline), int(r.n_hard), float(r.worst_hard),
-                            int(r.first_hard_sample), int(r.first_hard_iter), int(r.first_hard_kind))
+                            int(r.first_hard_sample), int(r.first_hard_iter), int(r.first_hard_kind),
+                            tuple(int(v) for v in r.border_by_kind), tuple(int(v) for v in r.hard_by_kind))
 
     def _check(self, rc, what):
         if rc != 0:
@@ -249,6 +255,14 @@ class OracleRun:
         r = self._replay(**replay)
         self._check(lib().orc_phase_converge(C.byref(self.P.c), _ptr(self.P.logc), C.byref(self.cc),
                                              C.byref(self.st), C.byref(r)), "converge")
+        return self._report(r)
+
+    def iterate(self, first: int, n: int = 1, **replay) -> ReplayReport:
+        """Continue Phase 1 (iterations first..first+n-1) from the current
+        positions, gradients and histories, without releasing."""
+        r = self._replay(**replay)
+        self._check(lib().orc_lbfgs_iterate(C.byref(self.P.c), _ptr(self.P.logc), C.byref(self.cc),
+                                            C.byref(self.st), int(first), int(n), C.byref(r)), "iterate")
         return self._report(r)
 
     def phase_stick(self, **replay) -> ReplayReport:

@@ -98,12 +98,18 @@ class Optimizer:
         L.check(self.lib.chisao_modes(self.h, 0, X.ctypes.data, F.ctypes.data, n.value, C.byref(n)), "chisao_modes")
         return ModeSet(X, F)
 
-    def get_state(self) -> dict:
-        N, d = self.N, self.d
+    def get_state(self, history: bool = False) -> dict:
+        N, d, m = self.N, self.d, int(self.cc.m)
         out = dict(X=np.zeros((N, d), np.float32), F=np.zeros(N, np.float32), G=np.zeros((N, d), np.float32),
                    stuck=np.zeros(N, np.uint8), active=np.zeros(N, np.uint8), stuck_pre=np.zeros(N, np.uint8),
                    removed=np.zeros(N, np.uint8), trace=np.zeros((self.n_conv + 1, N), np.uint8))
         s = L.State(*[out[f].ctypes.data for f in ("X", "F", "G", "stuck", "active", "stuck_pre", "removed", "trace")])
+        if history:
+            out.update(S=np.zeros((N, m, d), np.float32), Y=np.zeros((N, m, d), np.float32),
+                       rho=np.zeros((N, m), np.float32), head=np.zeros(N, np.int32), cnt=np.zeros(N, np.int32),
+                       conv=np.zeros(N, np.uint8))
+            for f in ("S", "Y", "rho", "head", "cnt", "conv"):
+                setattr(s, f, out[f].ctypes.data)
         L.check(self.lib.chisao_get_state(self.h, C.byref(s)), "chisao_get_state")
         out.update(k=s.k, gr_disabled=s.gr_disabled, gr_fail=s.gr_fail, gr_used_last=s.gr_used_last,
                    gr_prev_modes=s.gr_prev_modes)

@@ -467,6 +467,13 @@ extern "C" int chisao_get_state(chisao_handle h, chisao_state *s) {
     if (s->stuck_pre) HIP_TRY(hipMemcpy(s->stuck_pre, D.stuck_pre, N, hipMemcpyDeviceToHost));
     if (s->removed) HIP_TRY(hipMemcpy(s->removed, D.removed, N, hipMemcpyDeviceToHost));
     if (s->trace) HIP_TRY(hipMemcpy(s->trace, D.trace, N * (size_t)(D.n_conv + 1), hipMemcpyDeviceToHost));
+    const size_t m = D.m;
+    if (s->S) HIP_TRY(hipMemcpy(s->S, D.S, sizeof(float) * N * m * d, hipMemcpyDeviceToHost));
+    if (s->Y) HIP_TRY(hipMemcpy(s->Y, D.Y, sizeof(float) * N * m * d, hipMemcpyDeviceToHost));
+    if (s->rho) HIP_TRY(hipMemcpy(s->rho, D.rho, sizeof(float) * N * m, hipMemcpyDeviceToHost));
+    if (s->head) HIP_TRY(hipMemcpy(s->head, D.head, sizeof(int) * N, hipMemcpyDeviceToHost));
+    if (s->cnt) HIP_TRY(hipMemcpy(s->cnt, D.cnt, sizeof(int) * N, hipMemcpyDeviceToHost));
+    if (s->conv) HIP_TRY(hipMemcpy(s->conv, D.conv, N, hipMemcpyDeviceToHost));
     Ctl c;
     HIP_TRY(hipMemcpy(&c, D.ctl, sizeof c, hipMemcpyDeviceToHost));
     s->k = c.k;

@@ -581,8 +581,7 @@ __global__ void reseed_finalize_kernel(Dev D) {
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < nslots; j += gridDim.x * blockDim.x) {
         const int s = slots[j];
         if (kind == 3) D.active[s] = 0;
-        D.removed[s] = 0;
-        D.stuck[s] = 0;
+        D.stuck[s] = 0;  // removed[] keeps the deduplication decisions until the next cycle
         D.cnt[s] = 0;
         D.head[s] = D.m - 1;
         for (int c = 0; c < D.d; ++c) D.V[(size_t)s * D.d + c] = 0.0f;

@@ -124,5 +124,7 @@ def test_config3_shape_runs_every_phase():
     assert np.all(X >= prob.lo) and np.all(X <= prob.hi)
     for s in stats:
         assert s["n_modes"] + s["K_lost"] == s["n_stuck"]
+    for s in stats[:-1]:  # phases 4-6 do not run in the last cycle
         assert s["sigma"] == pytest.approx(0.1)
+        assert s["n_unfrozen"] > 0 and s["alpha_c"] > 0 and s["alpha_a"] > 0
     assert stats[0]["evals"] > 512 * 18
