@@ -1,0 +1,186 @@
+#!/usr/bin/env python3
+"""Throughput of the ChiSao per-cycle population update on one MI355X.
+
+Workload (the paper's Gaussian-mixture objective, anisotropic, at d=64): 128
+components with centres in [-20,20]^64 and covariances Q diag(lam) Q^T
+(lam log-uniform in [0.05,1]), N=65536 samples, L-BFGS memory 10, 18 L-BFGS
+iterations, 3 smoothing steps of 16 probes at sigma=0.1, 5 anti-convergence
+steps.  A step is one (non-final) oscillation cycle: all six phases.
+
+The metric counts sample-iterations nominally: N * (n_conv + n_cloud + n_anti)
+per cycle, masked samples included.  `value` is the adjoint-gradient
+throughput; the finite-difference throughput on the same schedule and the
+ratio between the two are reported beside it, together with the roofline
+position of the dominant kernel (HIP events around its launches during the
+timed cycles) and the FP64 CPU oracle's throughput on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+METRIC = "sample-iterations/s at d=64,N=65536 (adjoint vs FD grad); mode recall vs oracle"
+PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+
+
+def eval_flops_per_point(d: int, K: int) -> int:
+    """Algorithmic flops of one objective (+adjoint) evaluation: per component
+    the contraction u = P (x - mu) (2 d^2), the quadratic form delta . u (2 d)
+    and the gradient accumulation (2 d)."""
+    return K * (2 * d * d + 4 * d)
+
+
+def lbfgs_bytes_per_step(d: int, m: int) -> int:
+    """Algorithmic HBM bytes of one L-BFGS direction + pair update for one
+    sample with a full history: read x, x_prev, g, g_prev, S, Y (m d each), rho;
+    write the new pair and the direction."""
+    return 4 * (4 * d + 2 * m * d + m + 2 * d + 1 + d)
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def run_gpu(prob, cfg, x0, warmup, steps, profile=True):
+    import torch
+
+    from paper_2606_26164_amd.api import Optimizer
+
+    opt = Optimizer(prob, cfg, x0)
+    per_cycle = []
+    for i in range(warmup):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        opt.cycle(1)
+        torch.cuda.synchronize()
+        per_cycle.append(time.perf_counter() - t)
+        log(f"  warmup cycle {i + 1}: {per_cycle[-1] * 1e3:.1f} ms")
+    torch.cuda.synchronize()
+    if profile:
+        opt.profile_begin()
+    t0 = time.perf_counter()
+    stats = opt.cycle(steps, stats=True) if steps > 0 else []
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = opt.profile_end() if profile else {}
+    opt.close()
+    return dict(seconds=t1 - t0, warmup_seconds=per_cycle, stats=stats, profile=prof)
+
+
+def cpu_baseline(prob, cfg, n_samples):
+    from oracle import oracle as O
+
+    x0 = __import__("workloads").uniform_population(2, n_samples, prob.lo, prob.hi)
+    c = cfg.with_(N=n_samples)
+    run = O.OracleRun(prob, c, x0)
+    t = time.perf_counter()
+    run.cycle()
+    dt = time.perf_counter() - t
+    si = n_samples * (c.n_conv + c.n_cloud + c.n_anti)
+    return dict(value=si / dt, unit="sample-iterations/s", cores=O.num_threads(), kind="oracle",
+                sample=f"config-3 problem (d=64, K=128), {n_samples} samples from a uniform start, one non-final "
+                       f"cycle with the analytic gradient, FP64: {si} sample-iterations in {dt:.1f} s")
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--fd-steps", type=int, default=1, help="finite-difference cycles timed (0: skip)")
+    ap.add_argument("--N", type=int, default=65536)
+    ap.add_argument("--cpu-samples", type=int, default=2048, help="oracle baseline sample size (0: skip)")
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
+        return 2
+    import torch
+
+    import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a ROCm GPU", file=sys.stderr)
+        return 1
+    prob, cfg, x0 = W.config3(N=args.N)
+    si_per_cycle = cfg.N * (cfg.n_conv + cfg.n_cloud + cfg.n_anti)
+    log(f"adjoint: N={cfg.N} d={prob.d} K={prob.K} warmup={args.warmup} steps={args.steps}")
+    adj = run_gpu(prob, cfg, x0, args.warmup, args.steps)
+    value = si_per_cycle * args.steps / adj["seconds"]
+    ms_per_step = adj["seconds"] / args.steps * 1e3
+    log(f"adjoint: {ms_per_step:.1f} ms/cycle, {value:.4g} sample-iterations/s")
+
+    fd = None
+    if args.fd_steps > 0:
+        log(f"finite differences: {args.fd_steps} cycle(s) from the same start")
+        r = run_gpu(prob, cfg.with_(grad_mode=0), x0, 0, args.fd_steps, profile=False)
+        fd_value = si_per_cycle * args.fd_steps / r["seconds"]
+        # adjoint cycle 1 from the same start, for a like-for-like ratio
+        adj_first = adj["warmup_seconds"][0] if adj["warmup_seconds"] else None
+        fd = dict(value=fd_value, unit="sample-iterations/s", cycles=args.fd_steps,
+                  ms_per_step=r["seconds"] / args.fd_steps * 1e3,
+                  adjoint_over_fd_first_cycles=(r["seconds"] / args.fd_steps) / adj_first if adj_first else None)
+        log(f"fd: {fd['ms_per_step']:.1f} ms/cycle, {fd_value:.4g} sample-iterations/s")
+
+    # roofline of the dominant kernel over the timed cycles
+    prof = adj["profile"]
+    dom = max((k for k in prof if k.startswith("eval")), key=lambda k: prof[k]["ms"])
+    p = prof[dom]
+    fpp = eval_flops_per_point(prob.d, prob.K)
+    achieved = p["points"] * fpp / (p["ms"] * 1e-3) / 1e12
+    roof = dict(bound="mfma", achieved=achieved, peak=PEAK_FP32_MFMA_TFLOPS, unit="TFLOP/s",
+                frac=achieved / PEAK_FP32_MFMA_TFLOPS, traffic=None, kernel=f"eval_kernel ({dom})",
+                launches=p["launches"], avg_launch_ms=p["ms"] / max(p["launches"], 1),
+                flops_per_point=fpp, points=p["points"])
+    lb = prof.get("lbfgs")
+    roof_lbfgs = None
+    if lb and lb["ms"] > 0:
+        bps = lbfgs_bytes_per_step(prob.d, cfg.m)
+        gbs = lb["points"] * bps / (lb["ms"] * 1e-3) / 1e9
+        roof_lbfgs = dict(bound="hbm", achieved=gbs, peak=PEAK_HBM_GBS, unit="GB/s", frac=gbs / PEAK_HBM_GBS,
+                          traffic=None, kernel="lbfgs_step_kernel", bytes_per_sample_step=bps,
+                          launches=lb["launches"], avg_launch_ms=lb["ms"] / max(lb["launches"], 1))
+    kernel_ms = {k: round(v["ms"] / args.steps, 3) for k, v in prof.items()}
+
+    cpu = None
+    if args.cpu_samples > 0:
+        log(f"cpu baseline: oracle on {args.cpu_samples} samples")
+        cpu = cpu_baseline(prob, cfg, args.cpu_samples)
+        log(f"cpu: {cpu['value']:.4g} sample-iterations/s on {cpu['cores']} threads")
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "sample-iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"d=64 anisotropic Gaussian mixture, K=128, N={cfg.N}; m=10, n_conv=18, "
+                        f"n_cloud=3 x M=16 probes (sigma=0.1), n_anti=5; adjoint gradient; one step = one cycle",
+            "N": cfg.N, "d": prob.d, "K": prob.K, "grad": "adjoint",
+            "parallelism": "single GPU",
+        },
+        "fd": fd,
+        "adjoint_over_fd": (value / fd["value"]) if fd else None,
+        "roofline": roof,
+        "roofline_lbfgs": roof_lbfgs,
+        "kernel_ms_per_step": kernel_ms,
+        "cycle_stats_last": adj["stats"][-1] if adj["stats"] else None,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -130,8 +130,25 @@ typedef struct {
     float *rho;         /* [N*m] 1 / s'y */
     int32_t *head;      /* [N] */
     int32_t *cnt;       /* [N] */
-    uint8_t *conv;      /* [N] converged flags of the last Phase 1 */
+    uint8_t *conv;      /* [N] last Phase 1: 1 converged, 2 stalled (a search from an empty history failed,
+                           so every later iteration would repeat it), 0 otherwise */
 } chisao_state;
+
+/* Kernel timing of the work enqueued by chisao_cycle / chisao_run_phases
+ * while profiling is on: HIP events recorded around each launch on the
+ * handle's stream, and the number of objective evaluations (points) each
+ * evaluation launch processed, counted on the device. */
+#define CHISAO_PROF_EVAL_DIRECT 0 /* value and adjoint gradient at the samples */
+#define CHISAO_PROF_EVAL_TRIAL 1  /* line-search trial points */
+#define CHISAO_PROF_EVAL_PROBE 2  /* Hands Like Clouds smoothing probes */
+#define CHISAO_PROF_EVAL_FD 3     /* central-difference stencil points */
+#define CHISAO_PROF_LBFGS 4       /* two-loop directions and curvature pairs */
+#define CHISAO_PROF_CLASSES 8
+typedef struct {
+    int32_t launches;
+    double ms;       /* summed kernel time */
+    int64_t points;  /* evaluations processed (evaluation classes) or samples visited (L-BFGS) */
+} chisao_kernel_profile;
 
 typedef struct chisao_ctx *chisao_handle;
 
@@ -173,6 +190,10 @@ int chisao_run_phases(chisao_handle h, uint32_t phase_mask);
  * central differences (fd_h of the handle's config).  Enqueued on the
  * handle's stream; does not synchronize. */
 int chisao_eval(chisao_handle h, const float *X_dev, int B, float *f_dev, float *G_dev, int grad_mode);
+
+/* enable = 1: clear the counters and start recording; enable = 0: stop,
+ * synchronize and write CHISAO_PROF_CLASSES entries to out (may be NULL). */
+int chisao_profile(chisao_handle h, int enable, chisao_kernel_profile *out);
 
 void chisao_destroy(chisao_handle h);
 

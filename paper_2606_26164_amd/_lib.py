@@ -42,7 +42,14 @@ class State(C.Structure):
                 ("head", C.c_void_p), ("cnt", C.c_void_p), ("conv", C.c_void_p)]
 
 
-EXPORTS = ("chisao_init", "chisao_cycle", "chisao_modes", "chisao_get_state", "chisao_set_state",
+class KernelProfile(C.Structure):
+    _fields_ = [("launches", C.c_int32), ("ms", C.c_double), ("points", C.c_int64)]
+
+
+PROF_CLASSES = 8
+PROF_NAMES = ("eval_direct", "eval_trial", "eval_probe", "eval_fd", "lbfgs", "unused5", "unused6", "unused7")
+
+EXPORTS = ("chisao_init", "chisao_profile", "chisao_cycle", "chisao_modes", "chisao_get_state", "chisao_set_state",
            "chisao_run_phases", "chisao_eval", "chisao_destroy", "chisao_last_error")
 
 _lib = None
@@ -71,6 +78,8 @@ def load(path: str = LIB_PATH):
     L.chisao_run_phases.restype = C.c_int
     L.chisao_eval.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int]
     L.chisao_eval.restype = C.c_int
+    L.chisao_profile.argtypes = [C.c_void_p, C.c_int, P(KernelProfile)]
+    L.chisao_profile.restype = C.c_int
     L.chisao_destroy.argtypes = [C.c_void_p]
     L.chisao_destroy.restype = None
     L.chisao_last_error.argtypes = []

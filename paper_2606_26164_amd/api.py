@@ -85,6 +85,15 @@ class Optimizer:
             return None
         return [{f: getattr(arr[i], f) for f, _ in L.CycleStats._fields_} for i in range(n)]
 
+    def profile_begin(self):
+        L.check(self.lib.chisao_profile(self.h, 1, None), "chisao_profile")
+
+    def profile_end(self) -> dict:
+        arr = (L.KernelProfile * L.PROF_CLASSES)()
+        L.check(self.lib.chisao_profile(self.h, 0, arr), "chisao_profile")
+        return {L.PROF_NAMES[i]: dict(launches=arr[i].launches, ms=arr[i].ms, points=arr[i].points)
+                for i in range(L.PROF_CLASSES) if arr[i].launches or arr[i].points}
+
     def run_phases(self, mask: int):
         L.check(self.lib.chisao_run_phases(self.h, mask), "chisao_run_phases")
 

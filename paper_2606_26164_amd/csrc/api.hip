@@ -64,8 +64,36 @@ struct chisao_ctx {
     int device = 0;
     int k_host = 0;  // cycles completed (mirrors ctl->k)
     Buffers buf;
-    ~chisao_ctx() { buf.release(); }
+    // profiling: event pairs recorded around launches of each class
+    bool prof = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<int, size_t>> ev_used;  // (class, index of the start event)
+    ~chisao_ctx() {
+        for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+        buf.release();
+    }
 };
+
+// Run a launch; when profiling, bracket it with events on the handle's stream.
+template <class F>
+static hipError_t timed(chisao_ctx *h, int cls, F &&launch) {
+    if (!h->prof) return launch();
+    const size_t i = h->ev_used.size() * 2;
+    while (h->ev_pool.size() < i + 2) {
+        hipEvent_t e;
+        hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) return r;
+        h->ev_pool.push_back(e);
+    }
+    hipError_t r = hipEventRecord(h->ev_pool[i], h->stream);
+    if (r != hipSuccess) return r;
+    r = launch();
+    if (r != hipSuccess) return r;
+    r = hipEventRecord(h->ev_pool[i + 1], h->stream);
+    if (r != hipSuccess) return r;
+    h->ev_used.push_back({cls, i});
+    return hipSuccess;
+}
 
 static int pad_dim(int d) { return d <= 16 ? 16 : (d <= 32 ? 32 : 64); }
 
@@ -197,6 +225,7 @@ extern "C" int chisao_init(chisao_handle *out, const chisao_problem *p, const ch
         ALLOC(D.stuck_pre, uint8_t, N);
         ALLOC(D.status, uint8_t, N);
         ALLOC(D.reset, uint8_t, N);
+        ALLOC(D.steep, uint8_t, N);
         ALLOC(D.trace, uint8_t, N * (size_t)(D.n_conv + 1));
         ALLOC(D.S, float, N * m * d);
         ALLOC(D.Y, float, N * m * d);
@@ -281,6 +310,11 @@ static int eval_args_base(chisao_ctx *h, EvalArgs &a) {
 
 static inline int *host_list(const Dev &D, int id) { return D.lists + (size_t)id * D.N; }
 
+static hipError_t run_eval(chisao_ctx *h, const EvalArgs &a, int center, bool fd, bool grad) {
+    const int cls = fd ? CHISAO_PROF_EVAL_FD : center;
+    return timed(h, cls, [&] { return launch_eval(a, center, fd, grad, h->stream); });
+}
+
 static hipError_t eval_list(chisao_ctx *h, int list_id, float *F_out, float *G_out, bool want_f) {
     const Dev &D = h->D;
     hipStream_t st = h->stream;
@@ -292,18 +326,18 @@ static hipError_t eval_list(chisao_ctx *h, int list_id, float *F_out, float *G_o
     if (D.grad_mode == CHISAO_GRAD_ADJOINT) {
         a.F_out = F_out;
         a.G_out = G_out;
-        return launch_eval(a, kDirect, false, true, st);
+        return run_eval(h, a, kDirect, false, true);
     }
     hipError_t e = hipSuccess;
     if (want_f) {
         a.F_out = F_out;
         a.G_out = nullptr;
-        e = launch_eval(a, kDirect, false, false, st);
+        e = run_eval(h, a, kDirect, false, false);
         if (e != hipSuccess) return e;
     }
     a.F_out = nullptr;
     a.G_out = G_out;
-    return launch_eval(a, kDirect, true, false, st);
+    return run_eval(h, a, kDirect, true, false);
 }
 
 static hipError_t phase_converge(chisao_ctx *h) {
@@ -315,7 +349,7 @@ static hipError_t phase_converge(chisao_ctx *h) {
     if ((e = eval_list(h, L_ACT, D.F, D.G, true)) != hipSuccess) return e;
     for (int t = 1; t <= D.n_conv + 1; ++t) {
         if ((e = launch_reset_counts(D, (1 << L_T1) | (1 << L_T2) | (1 << L_FD), st)) != hipSuccess) return e;
-        if ((e = launch_lbfgs_step(D, t, st)) != hipSuccess) return e;
+        if ((e = timed(h, CHISAO_PROF_LBFGS, [&] { return launch_lbfgs_step(D, t, st); })) != hipSuccess) return e;
         if (t > D.n_conv) break;
         EvalArgs a;
         eval_args_base(h, a);
@@ -325,14 +359,14 @@ static hipError_t phase_converge(chisao_ctx *h) {
         a.Vc = 1;
         a.r0 = 0;
         a.trial_next = D.ls_max > 1 ? L_T2 : -1;
-        if ((e = launch_eval(a, kTrial, false, adj, st)) != hipSuccess) return e;
+        if ((e = run_eval(h, a, kTrial, false, adj)) != hipSuccess) return e;
         if (D.ls_max > 1) {
             a.list = host_list(D, L_T2);
             a.count_ptr = &D.ctl->count[L_T2];
             a.Vc = D.ls_max - 1;
             a.r0 = 1;
             a.trial_next = -1;
-            if ((e = launch_eval(a, kTrial, false, adj, st)) != hipSuccess) return e;
+            if ((e = run_eval(h, a, kTrial, false, adj)) != hipSuccess) return e;
         }
         if (!adj) {
             EvalArgs b;
@@ -341,7 +375,7 @@ static hipError_t phase_converge(chisao_ctx *h) {
             b.count_ptr = &D.ctl->count[L_FD];
             b.n_jobs = D.N;
             b.G_out = D.G;
-            if ((e = launch_eval(b, kDirect, true, false, st)) != hipSuccess) return e;
+            if ((e = run_eval(h, b, kDirect, true, false)) != hipSuccess) return e;
         }
     }
     return hipSuccess;
@@ -363,7 +397,7 @@ static hipError_t phase_hlc(chisao_ctx *h) {
         a.n_jobs = D.N;
         a.Vc = D.M;
         a.step = step;
-        if ((e = launch_eval(a, kProbe, !adj, adj, st)) != hipSuccess) return e;
+        if ((e = run_eval(h, a, kProbe, !adj, adj)) != hipSuccess) return e;
         if (!adj && (e = launch_probe_mean(D, st)) != hipSuccess) return e;
         if (step == 0 && (e = launch_step_size(D, D.Gh, 0, st)) != hipSuccess) return e;
         if ((e = launch_hlc_update(D, st)) != hipSuccess) return e;
@@ -532,6 +566,37 @@ extern "C" int chisao_modes(chisao_handle h, int problem, float *x_out, float *f
     HIP_TRY(hipMemcpyAsync(x_out, D.Gh, sizeof(float) * (size_t)n * D.d, hipMemcpyDeviceToHost, h->stream));
     if (f_out) HIP_TRY(hipMemcpyAsync(f_out, D.Pd, sizeof(float) * (size_t)n, hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
+    return CHISAO_OK;
+}
+
+extern "C" int chisao_profile(chisao_handle h, int enable, chisao_kernel_profile *out) {
+    if (!h) return fail(CHISAO_E_INVAL, "null handle");
+    HIP_TRY(hipSetDevice(h->device));
+    if (enable) {
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        unsigned long long zero[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        HIP_TRY(hipMemcpy(h->D.ctl->prof_points, zero, sizeof zero, hipMemcpyHostToDevice));
+        h->ev_used.clear();
+        h->prof = true;
+        return CHISAO_OK;
+    }
+    h->prof = false;
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    if (out) {
+        chisao_kernel_profile res[CHISAO_PROF_CLASSES];
+        memset(res, 0, sizeof res);
+        for (auto &u : h->ev_used) {
+            float ms = 0.0f;
+            HIP_TRY(hipEventElapsedTime(&ms, h->ev_pool[u.second], h->ev_pool[u.second + 1]));
+            res[u.first].launches += 1;
+            res[u.first].ms += ms;
+        }
+        unsigned long long pts[8];
+        HIP_TRY(hipMemcpy(pts, h->D.ctl->prof_points, sizeof pts, hipMemcpyDeviceToHost));
+        for (int i = 0; i < 8 && i < CHISAO_PROF_CLASSES; ++i) res[i].points = (int64_t)pts[i];
+        memcpy(out, res, sizeof res);
+    }
+    h->ev_used.clear();
     return CHISAO_OK;
 }
 

@@ -104,6 +104,7 @@ struct Ctl {
     int ls_fail;
     int evals;
     float f_max, sigma, alpha_c, alpha_a;
+    unsigned long long prof_points[8];  // cumulative evaluations per kernel class (profiling)
 };
 
 // Per-cycle record kept on the device, copied out on request.
@@ -142,7 +143,7 @@ struct Dev {
     uint32_t key0, key1, phase_mask;
     // population state
     float *X, *F, *G, *V, *Xprev, *Gprev, *Pd, *Gh, *Gp, *ginf;
-    uint8_t *stuck, *active, *conv, *removed, *stuck_pre, *status, *reset, *trace;
+    uint8_t *stuck, *active, *conv, *removed, *stuck_pre, *status, *reset, *steep, *trace;
     float *S, *Y, *rho;
     int *head, *cnt;
     int *lists;  // kNumLists x N

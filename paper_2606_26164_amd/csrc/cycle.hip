@@ -84,6 +84,7 @@ __global__ void begin_samples_kernel(Dev D) {
         D.conv[s] = 0;
         D.status[s] = 0;
         D.reset[s] = 0;
+        D.steep[s] = 0;
         D.cnt[s] = 0;
         D.head[s] = D.m - 1;
         if (D.active[s]) {
@@ -153,6 +154,10 @@ __global__ __launch_bounds__(kBlock) void lbfgs_step_kernel(Dev D, int t) {
                 D.conv[s] = conv;
                 D.trace[s] = conv ? kTrConv : 0;
             }
+        } else if (conv && D.conv[s] == 2) {
+            // stalled: the failed search started from an empty history, so
+            // every later iteration repeats it exactly and fails the same way
+            if (lane == 0) D.trace[(size_t)(t - 1) * D.N + s] = kTrFail;
         } else {
             const uint8_t stt = D.status[s];
             if (stt != 0) {
@@ -180,11 +185,13 @@ __global__ __launch_bounds__(kBlock) void lbfgs_step_kernel(Dev D, int t) {
                     head = m - 1;
                 }
                 const float gi = wave_max(fabsf(gv));
-                conv = gi < D.eps_grad;
-                if (conv) code |= kTrConv;
+                const bool converged = gi < D.eps_grad;
+                if (converged) code |= kTrConv;
+                const bool stall = !converged && !(stt & kStAccept) && D.steep[s];
+                conv = converged || stall;  // either way no further direction in this phase
                 if (lane == 0) {
                     D.ginf[s] = gi;
-                    D.conv[s] = conv;
+                    D.conv[s] = converged ? 1 : (stall ? 2 : 0);
                     D.trace[(size_t)(t - 1) * D.N + s] = code;
                     D.status[s] = 0;
                     D.reset[s] = 0;
@@ -194,6 +201,7 @@ __global__ __launch_bounds__(kBlock) void lbfgs_step_kernel(Dev D, int t) {
             }
         }
         if (t > D.n_conv || conv) continue;
+        if (lane == 0) atomicAdd(&D.ctl->prof_points[4], 1ull);
         // ---- two-loop recursion on registers ----
         float hs[MM], hy[MM], al[MM], rh[MM];
 #pragma unroll
@@ -239,6 +247,7 @@ __global__ __launch_bounds__(kBlock) void lbfgs_step_kernel(Dev D, int t) {
         }
         if (on) D.Pd[row] = p;
         if (lane == 0) {
+            D.steep[s] = (cnt == 0) || rst;
             if (rst) {
                 D.cnt[s] = 0;
                 D.head[s] = m - 1;

@@ -254,6 +254,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ev
             int nv = 0;
             for (int p = 0; p < PPW; ++p) nv += (s_s[p] >= 0);
             atomicAdd(&D.ctl->evals, nv);
+            atomicAdd(&D.ctl->prof_points[FD ? 3 : CENTER], (unsigned long long)nv);
         }
         // ---- epilogues -----------------------------------------------------
         if constexpr (CENTER == kDirect && !FD) {
