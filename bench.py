@@ -41,6 +41,35 @@ def lbfgs_bytes_per_step(d: int, m: int) -> int:
     return 4 * (4 * d + 2 * m * d + m + 2 * d + 1 + d)
 
 
+HERE = os.path.dirname(os.path.abspath(__file__))
+COUNTERS = os.path.join(HERE, "profiles", "eval_kernel_config3_counters.md")
+
+
+def eval_source_digest() -> str:
+    """Digest of the evaluation kernel's sources: hardware-counter figures are
+    only used while the kernel is the one they were taken from."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in ("eval.hip", "common.h", "kernels.h"):
+        with open(os.path.join(HERE, "paper_2606_26164_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary, or None when absent or taken from a different kernel source."""
+    try:
+        text = open(COUNTERS).read()
+    except OSError:
+        return None
+    vals = dict(ln.split(": ", 1) for ln in text.splitlines() if ln.startswith(("traffic_bytes", "eval_source")))
+    if vals.get("eval_source_sha256", "").strip() != eval_source_digest():
+        return None
+    return int(vals["traffic_bytes_per_launch"])
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -94,6 +123,9 @@ def main(argv=None):
     ap.add_argument("--fd-steps", type=int, default=1, help="finite-difference cycles timed (0: skip)")
     ap.add_argument("--N", type=int, default=65536)
     ap.add_argument("--cpu-samples", type=int, default=2048, help="oracle baseline sample size (0: skip)")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="before the timed cycles, copy a buffer of this size once (a reference kernel of known "
+                         "traffic for hardware-counter scaling)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
@@ -105,6 +137,14 @@ def main(argv=None):
     if not torch.cuda.is_available():
         print("bench.py needs a ROCm GPU", file=sys.stderr)
         return 1
+    if args.calib_copy_mib > 0:
+        n = args.calib_copy_mib * (1 << 20) // 4
+        src = torch.ones(n, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"reference copy: {args.calib_copy_mib} MiB read + {args.calib_copy_mib} MiB written")
+        del src, dst
     prob, cfg, x0 = W.config3(N=args.N)
     si_per_cycle = cfg.N * (cfg.n_conv + cfg.n_cloud + cfg.n_anti)
     log(f"adjoint: N={cfg.N} d={prob.d} K={prob.K} warmup={args.warmup} steps={args.steps}")
@@ -131,8 +171,10 @@ def main(argv=None):
     p = prof[dom]
     fpp = eval_flops_per_point(prob.d, prob.K)
     achieved = p["points"] * fpp / (p["ms"] * 1e-3) / 1e12
+    traffic = measured_traffic() if dom == "eval_probe" else None
     roof = dict(bound="mfma", achieved=achieved, peak=PEAK_FP32_MFMA_TFLOPS, unit="TFLOP/s",
-                frac=achieved / PEAK_FP32_MFMA_TFLOPS, traffic=None, kernel=f"eval_kernel ({dom})",
+                frac=achieved / PEAK_FP32_MFMA_TFLOPS, traffic=traffic, traffic_unit="bytes per launch",
+                kernel=f"eval_kernel ({dom})",
                 launches=p["launches"], avg_launch_ms=p["ms"] / max(p["launches"], 1),
                 flops_per_point=fpp, points=p["points"])
     lb = prof.get("lbfgs")
