@@ -88,7 +88,10 @@ typedef struct {
     uint32_t phase_mask;/* bit p enables phase p for p = 3..6 (ablation hook); 0x7E = all */
     uint64_t seed;      /* key of every random stream */
     uint32_t problem_id;/* mixed into the key, so problems draw independent streams */
+    uint32_t flags;     /* CHISAO_FLAG_* (handle-wide; taken from the first problem of a batch) */
 } chisao_config;
+
+#define CHISAO_FLAG_NO_GRAPH 1u /* enqueue every cycle's kernels one by one instead of replaying a captured hipGraph */
 
 /* Per-cycle statistics (host struct). */
 typedef struct {
@@ -160,28 +163,38 @@ typedef struct chisao_ctx *chisao_handle;
 int chisao_init(chisao_handle *out, const chisao_problem *p, const chisao_config *c, const float *x0_dev,
                 void *hip_stream);
 
-/* Run n_cycles oscillation cycles (Algorithm 1 body).  Phases 4-6 are
- * skipped in cycle n_osc.  Work is enqueued asynchronously; when stats_host is
- * not NULL the call synchronizes and fills n_cycles entries.  Running past
- * n_osc fails with CHISAO_E_STATE and runs nothing. */
+/* Several independent problems in one handle (one per entry of ps/cs, up to
+ * 256, uneven d, K and N allowed, equal n_osc): every kernel of a cycle covers
+ * all problems, and each problem computes exactly what it would compute in a
+ * handle of its own.  x0_dev: array of n_problems device pointers (entries may
+ * be NULL), or NULL for uniform draws.  Problem indices below refer to the
+ * order of ps. */
+int chisao_init_batched(chisao_handle *out, int n_problems, const chisao_problem *ps, const chisao_config *cs,
+                        const float *const *x0_dev, void *hip_stream);
+
+/* Run n_cycles oscillation cycles (Algorithm 1 body) of every problem.
+ * Phases 4-6 are skipped in cycle n_osc.  Work is enqueued asynchronously (by
+ * default as one captured hipGraph per cycle); when stats_host is not NULL the
+ * call synchronizes and fills n_cycles * n_problems entries, cycle-major.
+ * Running past n_osc fails with CHISAO_E_STATE and runs nothing. */
 int chisao_cycle(chisao_handle h, int n_cycles, chisao_cycle_stats *stats_host);
 
 /* The estimated mode set {x_i : stuck_i} (Algorithm 1 return value):
  * synchronizes, then writes the stuck active samples in ascending index to
  * x_out (host [cap*d]) and f_out (host [cap], may be NULL).  *n_out receives
  * the count; if cap is smaller, nothing is written and CHISAO_E_RANGE is
- * returned.  problem must be 0. */
+ * returned.  problem: index within the handle. */
 int chisao_modes(chisao_handle h, int problem, float *x_out, float *f_out, int cap, int *n_out);
 
 /* Copy the state to / from host memory (synchronizes).  set_state writes X,
  * stuck, active, k and the Golden Rooster state; F, G and the decision arrays
  * are recomputed by the next cycle. */
-int chisao_get_state(chisao_handle h, chisao_state *s);
-int chisao_set_state(chisao_handle h, const chisao_state *s);
+int chisao_get_state(chisao_handle h, int problem, chisao_state *s);
+int chisao_set_state(chisao_handle h, int problem, const chisao_state *s);
 
-/* Run a subset of the phases of cycle k+1 on the current state without
- * advancing k (test hook for per-phase parity).  phase_mask bit p selects
- * phase p (1..6); phases run in ascending order.  Synchronizes. */
+/* Run a subset of the phases of cycle k+1 of every problem on the current
+ * state without advancing k (test hook for per-phase parity).  phase_mask bit
+ * p selects phase p (1..6); phases run in ascending order.  Synchronizes. */
 int chisao_run_phases(chisao_handle h, uint32_t phase_mask);
 
 /* Batched objective on caller memory (Sec. 3.1 objective, with the gradient
@@ -189,7 +202,8 @@ int chisao_run_phases(chisao_handle h, uint32_t phase_mask);
  * G_dev device [B*d] (may be NULL).  grad_mode selects the adjoint kernel or
  * central differences (fd_h of the handle's config).  Enqueued on the
  * handle's stream; does not synchronize. */
-int chisao_eval(chisao_handle h, const float *X_dev, int B, float *f_dev, float *G_dev, int grad_mode);
+int chisao_eval(chisao_handle h, int problem, const float *X_dev, int B, float *f_dev, float *G_dev,
+                int grad_mode);
 
 /* enable = 1: clear the counters and start recording; enable = 0: stop,
  * synchronize and write CHISAO_PROF_CLASSES entries to out (may be NULL). */

@@ -10,6 +10,7 @@ LIB_PATH = os.path.join(HERE, "libchisao.so")
 OK, E_INVAL, E_NOMEM, E_DEVICE, E_STATE, E_RANGE = 0, -1, -2, -3, -4, -5
 GAUSS, STUDENT_T = 0, 1
 GRAD_FD, GRAD_ADJOINT = 0, 1
+FLAG_NO_GRAPH = 1
 
 
 class Problem(C.Structure):
@@ -24,7 +25,8 @@ class Config(C.Structure):
                 ("eps_dup", C.c_float), ("log_delta", C.c_float), ("momentum", C.c_float), ("alpha", C.c_float),
                 ("sigma", C.c_float), ("sigma_c", C.c_float), ("grad_mode", C.c_int32), ("fd_h", C.c_float),
                 ("ls_c1", C.c_float), ("ls_max", C.c_int32), ("curv_eps", C.c_float), ("gate_reps", C.c_int32),
-                ("phase_mask", C.c_uint32), ("seed", C.c_uint64), ("problem_id", C.c_uint32)]
+                ("phase_mask", C.c_uint32), ("seed", C.c_uint64), ("problem_id", C.c_uint32),
+                ("flags", C.c_uint32)]
 
 
 class CycleStats(C.Structure):
@@ -49,7 +51,7 @@ class KernelProfile(C.Structure):
 PROF_CLASSES = 8
 PROF_NAMES = ("eval_direct", "eval_trial", "eval_probe", "eval_fd", "lbfgs", "unused5", "unused6", "unused7")
 
-EXPORTS = ("chisao_init", "chisao_profile", "chisao_cycle", "chisao_modes", "chisao_get_state", "chisao_set_state",
+EXPORTS = ("chisao_init", "chisao_init_batched", "chisao_profile", "chisao_cycle", "chisao_modes", "chisao_get_state", "chisao_set_state",
            "chisao_run_phases", "chisao_eval", "chisao_destroy", "chisao_last_error")
 
 _lib = None
@@ -66,17 +68,19 @@ def load(path: str = LIB_PATH):
     P = C.POINTER
     L.chisao_init.argtypes = [P(C.c_void_p), P(Problem), P(Config), C.c_void_p, C.c_void_p]
     L.chisao_init.restype = C.c_int
+    L.chisao_init_batched.argtypes = [P(C.c_void_p), C.c_int, P(Problem), P(Config), P(C.c_void_p), C.c_void_p]
+    L.chisao_init_batched.restype = C.c_int
     L.chisao_cycle.argtypes = [C.c_void_p, C.c_int, P(CycleStats)]
     L.chisao_cycle.restype = C.c_int
     L.chisao_modes.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int, P(C.c_int)]
     L.chisao_modes.restype = C.c_int
-    L.chisao_get_state.argtypes = [C.c_void_p, P(State)]
+    L.chisao_get_state.argtypes = [C.c_void_p, C.c_int, P(State)]
     L.chisao_get_state.restype = C.c_int
-    L.chisao_set_state.argtypes = [C.c_void_p, P(State)]
+    L.chisao_set_state.argtypes = [C.c_void_p, C.c_int, P(State)]
     L.chisao_set_state.restype = C.c_int
     L.chisao_run_phases.argtypes = [C.c_void_p, C.c_uint32]
     L.chisao_run_phases.restype = C.c_int
-    L.chisao_eval.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int]
+    L.chisao_eval.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int]
     L.chisao_eval.restype = C.c_int
     L.chisao_profile.argtypes = [C.c_void_p, C.c_int, P(KernelProfile)]
     L.chisao_profile.restype = C.c_int

@@ -1,18 +1,21 @@
 // Host side of libchisao: the C ABI declared in include/chisao.h.
 //
-// A handle owns the device workspace of one population.  A cycle is a fixed
-// sequence of kernel launches on the handle's stream; every data-dependent
-// choice inside it (which samples move, line-search outcomes, Repulse Monkey
-// or Golden Rooster, step lengths) is read by the kernels from device
-// memory, so the host never waits inside a cycle.
+// A handle owns the device workspace of P independent problems.  A cycle is
+// a fixed sequence of kernel launches; every data-dependent choice inside it
+// (which samples move, line-search outcomes, Repulse Monkey or Golden
+// Rooster, step lengths) is read by the kernels from device memory, so the
+// host never waits inside a cycle and the sequence can be captured once into
+// a hipGraph and replayed for every cycle.
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <new>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/chisao.h"
@@ -35,10 +38,10 @@ int fail(int code, const char *fmt, ...) {
     return code;
 }
 
-#define HIP_TRY(expr)                                                                                   \
-    do {                                                                                                \
-        hipError_t e_ = (expr);                                                                         \
-        if (e_ != hipSuccess) return fail(CHISAO_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_));     \
+#define HIP_TRY(expr)                                                                               \
+    do {                                                                                            \
+        hipError_t e_ = (expr);                                                                     \
+        if (e_ != hipSuccess) return fail(CHISAO_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
 
 struct Buffers {
@@ -56,20 +59,47 @@ struct Buffers {
     }
 };
 
+int pad_dim(int d) { return d <= 16 ? 16 : (d <= 32 ? 32 : 64); }
+int coords_per_lane(int d) { return d <= 16 ? 1 : (d <= 32 ? 2 : 4); }
+
 }  // namespace
+
+// A group of problems served by one evaluation launch.
+struct EvalClass {
+    int DP, family, grad_mode;
+    const int *pids_dev;  // into the handle's class table
+    std::vector<int> pids;
+};
+// A group of samples served by one L-BFGS launch.
+struct LbfgsClass {
+    int cpl;
+    const int *samples_dev;  // nullptr: every sample of the handle
+    int n;
+};
 
 struct chisao_ctx {
     Dev D{};
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;  // the caller's stream: all work runs here
+    hipStream_t cur = nullptr;     // where launches are enqueued (stream, or the capture stream)
+    hipStream_t cap = nullptr;     // private stream for graph capture
     int device = 0;
-    int k_host = 0;  // cycles completed (mirrors ctl->k)
+    int k_host = 0;  // cycles completed
+    uint32_t flags = 0;
+    std::vector<ProblemDesc> pdh;  // host copy of the descriptors
+    std::vector<EvalClass> eclasses;
+    std::vector<LbfgsClass> lclasses;
+    const int *pid_seq = nullptr;  // device [P]: 0, 1, ..., P-1
     Buffers buf;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};  // [0]: cycles before n_osc, [1]: the last cycle
     // profiling: event pairs recorded around launches of each class
     bool prof = false;
     std::vector<hipEvent_t> ev_pool;
-    std::vector<std::pair<int, size_t>> ev_used;  // (class, index of the start event)
+    std::vector<std::pair<int, size_t>> ev_used;
     ~chisao_ctx() {
+        for (hipGraphExec_t g : graph)
+            if (g) (void)hipGraphExecDestroy(g);
         for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+        if (cap) (void)hipStreamDestroy(cap);
         buf.release();
     }
 };
@@ -85,139 +115,275 @@ static hipError_t timed(chisao_ctx *h, int cls, F &&launch) {
         if (r != hipSuccess) return r;
         h->ev_pool.push_back(e);
     }
-    hipError_t r = hipEventRecord(h->ev_pool[i], h->stream);
+    hipError_t r = hipEventRecord(h->ev_pool[i], h->cur);
     if (r != hipSuccess) return r;
     r = launch();
     if (r != hipSuccess) return r;
-    r = hipEventRecord(h->ev_pool[i + 1], h->stream);
+    r = hipEventRecord(h->ev_pool[i + 1], h->cur);
     if (r != hipSuccess) return r;
     h->ev_used.push_back({cls, i});
     return hipSuccess;
 }
 
-static int pad_dim(int d) { return d <= 16 ? 16 : (d <= 32 ? 32 : 64); }
-
-static int validate(const chisao_problem *p, const chisao_config *c) {
+// ---------------------------------------------------------------------------
+// Validation
+// ---------------------------------------------------------------------------
+static int validate(const chisao_problem *p, const chisao_config *c, int idx) {
     if (!p || !c) return fail(CHISAO_E_INVAL, "null problem or config");
-    if (p->family != CHISAO_GAUSS && p->family != CHISAO_STUDENT_T) return fail(CHISAO_E_INVAL, "unknown family");
-    if (p->d < 1 || p->d > 64) return fail(CHISAO_E_INVAL, "d must be in 1..64 (got %d)", p->d);
-    if (p->K < 1) return fail(CHISAO_E_INVAL, "K must be >= 1");
-    if (!p->log_w || !p->mu || !p->prec || !p->lo || !p->hi) return fail(CHISAO_E_INVAL, "null problem array");
+    if (p->family != CHISAO_GAUSS && p->family != CHISAO_STUDENT_T)
+        return fail(CHISAO_E_INVAL, "problem %d: unknown family", idx);
+    if (p->d < 1 || p->d > 64) return fail(CHISAO_E_INVAL, "problem %d: d must be in 1..64 (got %d)", idx, p->d);
+    if (p->K < 1) return fail(CHISAO_E_INVAL, "problem %d: K must be >= 1", idx);
+    if (!p->log_w || !p->mu || !p->prec || !p->lo || !p->hi)
+        return fail(CHISAO_E_INVAL, "problem %d: null problem array", idx);
     if (p->family == CHISAO_STUDENT_T && !(p->nu > 0.0f && isfinite(p->nu)))
-        return fail(CHISAO_E_INVAL, "Student-t needs nu > 0");
-    if (p->noise_sigma != 0.0f) return fail(CHISAO_E_INVAL, "noisy objectives are not supported in this version");
+        return fail(CHISAO_E_INVAL, "problem %d: Student-t needs nu > 0", idx);
+    if (p->noise_sigma != 0.0f)
+        return fail(CHISAO_E_INVAL, "problem %d: noisy objectives are not supported in this version", idx);
     const int d = p->d, K = p->K;
     for (int j = 0; j < d; ++j)
         if (!(isfinite(p->lo[j]) && isfinite(p->hi[j]) && p->lo[j] < p->hi[j]))
-            return fail(CHISAO_E_INVAL, "box bounds must be finite with lo < hi (coordinate %d)", j);
+            return fail(CHISAO_E_INVAL, "problem %d: box bounds must be finite with lo < hi (coordinate %d)", idx, j);
     for (int k = 0; k < K; ++k) {
-        if (!isfinite(p->log_w[k])) return fail(CHISAO_E_INVAL, "non-finite log weight %d", k);
+        if (!isfinite(p->log_w[k])) return fail(CHISAO_E_INVAL, "problem %d: non-finite log weight %d", idx, k);
         for (int j = 0; j < d; ++j)
-            if (!isfinite(p->mu[(size_t)k * d + j])) return fail(CHISAO_E_INVAL, "non-finite centre %d", k);
+            if (!isfinite(p->mu[(size_t)k * d + j])) return fail(CHISAO_E_INVAL, "problem %d: non-finite centre %d", idx, k);
         const float *P = p->prec + (size_t)k * d * d;
         for (int i = 0; i < d; ++i)
             for (int j = 0; j < d; ++j) {
-                if (!isfinite(P[i * d + j])) return fail(CHISAO_E_INVAL, "non-finite precision entry in %d", k);
-                if (P[i * d + j] != P[j * d + i]) return fail(CHISAO_E_INVAL, "precision matrix %d not symmetric", k);
+                if (!isfinite(P[i * d + j]))
+                    return fail(CHISAO_E_INVAL, "problem %d: non-finite precision entry in component %d", idx, k);
+                if (P[i * d + j] != P[j * d + i])
+                    return fail(CHISAO_E_INVAL, "problem %d: precision matrix %d not symmetric", idx, k);
             }
     }
-    if (c->N < 1) return fail(CHISAO_E_INVAL, "N must be >= 1");
-    if ((long)c->N * d > (1L << 31) - 1) return fail(CHISAO_E_INVAL, "N*d too large");
-    if (c->m < 1 || c->m > 32) return fail(CHISAO_E_INVAL, "m must be in 1..32");
-    if (c->n_osc < 1) return fail(CHISAO_E_INVAL, "n_osc must be >= 1");
-    if (c->n_anti < 0 || c->n_cloud < 0) return fail(CHISAO_E_INVAL, "negative step count");
-    if (c->M < 1 || c->M > 32) return fail(CHISAO_E_INVAL, "M must be in 1..32");
-    if (c->ls_max < 1 || c->ls_max > 16) return fail(CHISAO_E_INVAL, "ls_max must be in 1..16");
+    if (c->N < 1) return fail(CHISAO_E_INVAL, "problem %d: N must be >= 1", idx);
+    if (c->m < 1 || c->m > 32) return fail(CHISAO_E_INVAL, "problem %d: m must be in 1..32", idx);
+    if (c->n_osc < 1) return fail(CHISAO_E_INVAL, "problem %d: n_osc must be >= 1", idx);
+    if (c->n_anti < 0 || c->n_cloud < 0) return fail(CHISAO_E_INVAL, "problem %d: negative step count", idx);
+    if (c->M < 1 || c->M > 32) return fail(CHISAO_E_INVAL, "problem %d: M must be in 1..32", idx);
+    if (c->ls_max < 1 || c->ls_max > 16) return fail(CHISAO_E_INVAL, "problem %d: ls_max must be in 1..16", idx);
     if (c->grad_mode != CHISAO_GRAD_FD && c->grad_mode != CHISAO_GRAD_ADJOINT)
-        return fail(CHISAO_E_INVAL, "unknown grad_mode");
-    if (c->gate_reps != 0) return fail(CHISAO_E_INVAL, "gate_reps is reserved and must be 0");
-    if (!(c->eps_grad > 0.0f) || !(c->eps_dup > 0.0f)) return fail(CHISAO_E_INVAL, "eps_grad and eps_dup must be > 0");
+        return fail(CHISAO_E_INVAL, "problem %d: unknown grad_mode", idx);
+    if (c->gate_reps != 0) return fail(CHISAO_E_INVAL, "problem %d: gate_reps is reserved and must be 0", idx);
+    if (!(c->eps_grad > 0.0f) || !(c->eps_dup > 0.0f))
+        return fail(CHISAO_E_INVAL, "problem %d: eps_grad and eps_dup must be > 0", idx);
     if (!isfinite(c->log_delta) || !isfinite(c->momentum) || !isfinite(c->alpha) || !isfinite(c->sigma) ||
         !isfinite(c->sigma_c) || !isfinite(c->fd_h) || !isfinite(c->ls_c1) || !isfinite(c->curv_eps))
-        return fail(CHISAO_E_INVAL, "non-finite hyperparameter");
+        return fail(CHISAO_E_INVAL, "problem %d: non-finite hyperparameter", idx);
     return CHISAO_OK;
 }
 
 extern "C" const char *chisao_last_error(void) { return g_err.c_str(); }
 
-extern "C" int chisao_init(chisao_handle *out, const chisao_problem *p, const chisao_config *c, const float *x0_dev,
-                           void *hip_stream) {
+// ---------------------------------------------------------------------------
+// Creation
+// ---------------------------------------------------------------------------
+extern "C" int chisao_init_batched(chisao_handle *out, int n_problems, const chisao_problem *ps,
+                                   const chisao_config *cs, const float *const *x0_dev, void *hip_stream) {
     if (!out) return fail(CHISAO_E_INVAL, "null output handle");
     *out = nullptr;
-    int rc = validate(p, c);
-    if (rc) return rc;
+    if (n_problems < 1 || n_problems > 256) return fail(CHISAO_E_INVAL, "n_problems must be in 1..256");
+    if (!ps || !cs) return fail(CHISAO_E_INVAL, "null problem or config array");
+    int rc;
+    long NT = 0;
+    int DS = 1, mmax = 1, Mmax = 1, ncmax = 0;
+    std::vector<int> n_conv(n_problems);
+    for (int p = 0; p < n_problems; ++p) {
+        if ((rc = validate(&ps[p], &cs[p], p))) return rc;
+        if (cs[p].n_osc != cs[0].n_osc) return fail(CHISAO_E_INVAL, "all problems of a batch need the same n_osc");
+        NT += cs[p].N;
+        DS = std::max(DS, ps[p].d);
+        mmax = std::max(mmax, cs[p].m);
+        Mmax = std::max(Mmax, cs[p].M);
+        n_conv[p] = cs[p].n_conv > 0 ? cs[p].n_conv
+                                      : std::max(10, (int)ceil(3.0 * log2((double)ps[p].d) - 1e-9));
+        ncmax = std::max(ncmax, n_conv[p]);
+    }
+    if (NT * (long)DS * std::max(mmax, Mmax) > (1L << 31) - 1)
+        return fail(CHISAO_E_INVAL, "population too large for 32-bit indexing");
     chisao_ctx *h = new (std::nothrow) chisao_ctx();
     if (!h) return fail(CHISAO_E_NOMEM, "host allocation failed");
     h->stream = (hipStream_t)hip_stream;
-    HIP_TRY(hipGetDevice(&h->device));
+    h->cur = h->stream;
+    h->flags = cs[0].flags;
     Dev &D = h->D;
-    D.d = p->d;
-    D.DP = pad_dim(p->d);
-    D.K = p->K;
-    D.family = p->family;
-    D.nu = p->family == CHISAO_STUDENT_T ? p->nu : 1.0f;
-    D.nu_plus_d = D.nu + (float)p->d;
-    D.N = c->N;
-    D.m = c->m;
-    D.n_osc = c->n_osc;
-    D.n_conv = c->n_conv > 0 ? c->n_conv : std::max(10, (int)ceil(3.0 * log2((double)p->d) - 1e-9));
-    D.n_anti = c->n_anti;
-    D.n_cloud = c->n_cloud;
-    D.M = c->M;
-    D.ls_max = c->ls_max;
-    D.grad_mode = c->grad_mode;
-    D.eps_grad = c->eps_grad;
-    D.eps_dup = c->eps_dup;
-    D.log_delta = c->log_delta;
-    D.momentum = c->momentum;
-    D.alpha = c->alpha;
-    D.sigma_cfg = c->sigma;
-    D.sigma_c = c->sigma_c;
-    D.fd_h = c->fd_h;
-    D.ls_c1 = c->ls_c1;
-    D.curv_eps = c->curv_eps;
-    D.key0 = (uint32_t)(c->seed & 0xFFFFFFFFu);
-    D.key1 = (uint32_t)(c->seed >> 32) ^ c->problem_id;
-    D.phase_mask = c->phase_mask;
-    D.n_part_blocks = 256;
+    D.P = n_problems;
+    D.NT = (int)NT;
+    D.DS = DS;
+    D.mmax = mmax;
+    D.Mmax = Mmax;
+    D.n_conv_max = ncmax;
+    D.n_osc = cs[0].n_osc;
+    D.n_part_blocks = 64;
+    bool any_fd = false;
+    for (int p = 0; p < n_problems; ++p) any_fd |= cs[p].grad_mode == CHISAO_GRAD_FD;
 
-    const size_t N = (size_t)c->N, d = (size_t)p->d, K = (size_t)p->K, DP = (size_t)D.DP, m = (size_t)c->m;
+    const size_t N = (size_t)NT, P = (size_t)n_problems;
     Buffers &B = h->buf;
+    hipError_t e;
     auto A = [&](void **ptr, size_t bytes) -> int {
-        hipError_t e = B.alloc(ptr, bytes);
-        if (e != hipSuccess) return fail(CHISAO_E_NOMEM, "hipMalloc(%zu bytes): %s", bytes, hipGetErrorString(e));
+        hipError_t r = B.alloc(ptr, bytes);
+        if (r != hipSuccess) return fail(CHISAO_E_NOMEM, "hipMalloc(%zu bytes): %s", bytes, hipGetErrorString(r));
         return CHISAO_OK;
     };
-#define ALLOC(field, type, count)                                       \
-    do {                                                                \
-        void *tmp_;                                                     \
+#define ALLOC(field, type, count)                                           \
+    do {                                                                    \
+        void *tmp_;                                                         \
         if ((rc = A(&tmp_, sizeof(type) * (size_t)(count)))) goto fail_out; \
-        field = (type *)tmp_;                                           \
+        field = (type *)tmp_;                                               \
+    } while (0)
+#define HIP_GO(expr)                                                           \
+    do {                                                                       \
+        if ((e = (expr)) != hipSuccess) {                                      \
+            rc = fail(CHISAO_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e)); \
+            goto fail_out;                                                     \
+        }                                                                      \
     } while (0)
     {
-        float *Pfrag, *muB, *muC, *logc2, *lo, *hi, *tmp_w, *tmp_mu, *tmp_prec;
+        hipStream_t st = h->stream;
+        HIP_GO(hipGetDevice(&h->device));
         int *bad;
-        ALLOC(Pfrag, float, K * DP * DP);
-        ALLOC(muB, float, K * DP);
-        ALLOC(muC, float, K * DP);
-        ALLOC(logc2, float, K);
-        ALLOC(lo, float, d);
-        ALLOC(hi, float, d);
-        ALLOC(tmp_w, float, K);
-        ALLOC(tmp_mu, float, K * d);
-        ALLOC(tmp_prec, float, K * d * d);
         ALLOC(bad, int, 1);
-        D.Pfrag = Pfrag; D.muB = muB; D.muC = muC; D.logc2 = logc2; D.lo = lo; D.hi = hi;
-        ALLOC(D.X, float, N * d);
+        HIP_GO(hipMemsetAsync(bad, 0, sizeof(int), st));
+        // ---- per-problem constants ----
+        h->pdh.resize(P);
+        int s0 = 0;
+        for (int p = 0; p < n_problems; ++p) {
+            const chisao_problem &pr = ps[p];
+            const chisao_config &c = cs[p];
+            const size_t d = pr.d, K = pr.K, DP = pad_dim(pr.d);
+            ProblemDesc &q = h->pdh[p];
+            memset(&q, 0, sizeof q);
+            float *Pfrag, *muB, *muC, *logc2, *lo, *hi, *tw, *tmu, *tprec;
+            ALLOC(Pfrag, float, K * DP * DP);
+            ALLOC(muB, float, K * DP);
+            ALLOC(muC, float, K * DP);
+            ALLOC(logc2, float, K);
+            ALLOC(lo, float, d);
+            ALLOC(hi, float, d);
+            ALLOC(tw, float, K);
+            ALLOC(tmu, float, K * d);
+            ALLOC(tprec, float, K * d * d);
+            HIP_GO(hipMemcpyAsync(lo, pr.lo, sizeof(float) * d, hipMemcpyHostToDevice, st));
+            HIP_GO(hipMemcpyAsync(hi, pr.hi, sizeof(float) * d, hipMemcpyHostToDevice, st));
+            HIP_GO(hipMemcpyAsync(tw, pr.log_w, sizeof(float) * K, hipMemcpyHostToDevice, st));
+            HIP_GO(hipMemcpyAsync(tmu, pr.mu, sizeof(float) * K * d, hipMemcpyHostToDevice, st));
+            HIP_GO(hipMemcpyAsync(tprec, pr.prec, sizeof(float) * K * d * d, hipMemcpyHostToDevice, st));
+            const float nu = pr.family == CHISAO_STUDENT_T ? pr.nu : 1.0f;
+            HIP_GO(launch_prepare(pr.family, pr.d, (int)DP, pr.K, nu, tw, tmu, tprec, logc2, Pfrag, muB, muC, bad, st));
+            q.d = pr.d;
+            q.DP = (int)DP;
+            q.K = pr.K;
+            q.family = pr.family;
+            q.nu = nu;
+            q.nu_plus_d = nu + (float)pr.d;
+            q.Pfrag = Pfrag;
+            q.muB = muB;
+            q.muC = muC;
+            q.logc2 = logc2;
+            q.lo = lo;
+            q.hi = hi;
+            q.N = c.N;
+            q.s0 = s0;
+            s0 += c.N;
+            q.m = c.m;
+            q.n_conv = n_conv[p];
+            q.n_anti = c.n_anti;
+            q.n_cloud = c.n_cloud;
+            q.M = c.M;
+            q.ls_max = c.ls_max;
+            q.grad_mode = c.grad_mode;
+            q.eps_grad = c.eps_grad;
+            q.eps_dup = c.eps_dup;
+            q.log_delta = c.log_delta;
+            q.momentum = c.momentum;
+            q.alpha = c.alpha;
+            q.sigma_cfg = c.sigma;
+            q.sigma_c = c.sigma_c;
+            q.fd_h = c.fd_h;
+            q.ls_c1 = c.ls_c1;
+            q.curv_eps = c.curv_eps;
+            q.key0 = (uint32_t)(c.seed & 0xFFFFFFFFu);
+            q.key1 = (uint32_t)(c.seed >> 32) ^ c.problem_id;
+            q.phase_mask = c.phase_mask;
+        }
+        ProblemDesc *pd_dev;
+        ALLOC(pd_dev, ProblemDesc, P);
+        HIP_GO(hipMemcpyAsync(pd_dev, h->pdh.data(), sizeof(ProblemDesc) * P, hipMemcpyHostToDevice, st));
+        D.pd = pd_dev;
+        std::vector<uint16_t> pid(N);
+        for (int p = 0; p < n_problems; ++p)
+            for (int i = 0; i < h->pdh[p].N; ++i) pid[h->pdh[p].s0 + i] = (uint16_t)p;
+        uint16_t *pid_dev;
+        ALLOC(pid_dev, uint16_t, N);
+        HIP_GO(hipMemcpyAsync(pid_dev, pid.data(), sizeof(uint16_t) * N, hipMemcpyHostToDevice, st));
+        D.pid = pid_dev;
+        // ---- launch classes ----
+        std::map<std::tuple<int, int, int>, std::vector<int>> ecl;
+        std::map<int, std::vector<int>> lcl;
+        for (int p = 0; p < n_problems; ++p) {
+            ecl[{h->pdh[p].DP, h->pdh[p].family, h->pdh[p].grad_mode}].push_back(p);
+            lcl[coords_per_lane(h->pdh[p].d)].push_back(p);
+        }
+        std::vector<int> table;
+        for (int p = 0; p < n_problems; ++p) table.push_back(p);  // pid_seq
+        for (auto &kv : ecl) table.insert(table.end(), kv.second.begin(), kv.second.end());
+        std::vector<std::vector<int>> lsamples;
+        for (auto &kv : lcl) {
+            std::vector<int> v;
+            if (lcl.size() > 1)
+                for (int p : kv.second)
+                    for (int i = 0; i < h->pdh[p].N; ++i) v.push_back(h->pdh[p].s0 + i);
+            lsamples.push_back(v);
+        }
+        size_t tot = table.size();
+        for (auto &v : lsamples) tot += v.size();
+        int *tab_dev;
+        ALLOC(tab_dev, int, tot);
+        {
+            std::vector<int> all(table);
+            for (auto &v : lsamples) all.insert(all.end(), v.begin(), v.end());
+            HIP_GO(hipMemcpyAsync(tab_dev, all.data(), sizeof(int) * all.size(), hipMemcpyHostToDevice, st));
+            HIP_GO(hipStreamSynchronize(st));  // the host vectors go out of scope
+        }
+        h->pid_seq = tab_dev;
+        size_t off = P;
+        for (auto &kv : ecl) {
+            EvalClass c;
+            std::tie(c.DP, c.family, c.grad_mode) = kv.first;
+            c.pids = kv.second;
+            c.pids_dev = tab_dev + off;
+            off += kv.second.size();
+            h->eclasses.push_back(c);
+        }
+        size_t li = 0;
+        for (auto &kv : lcl) {
+            LbfgsClass c;
+            c.cpl = kv.first;
+            if (lcl.size() > 1) {
+                c.samples_dev = tab_dev + off;
+                c.n = (int)lsamples[li].size();
+                off += lsamples[li].size();
+            } else {
+                c.samples_dev = nullptr;
+                c.n = (int)N;
+            }
+            ++li;
+            h->lclasses.push_back(c);
+        }
+        // ---- population state ----
+        const size_t DSz = (size_t)DS;
+        ALLOC(D.X, float, N * DSz);
         ALLOC(D.F, float, N);
-        ALLOC(D.G, float, N * d);
-        ALLOC(D.V, float, N * d);
-        ALLOC(D.Xprev, float, N * d);
-        ALLOC(D.Gprev, float, N * d);
-        ALLOC(D.Pd, float, N * d);
-        ALLOC(D.Gh, float, N * d);
+        ALLOC(D.G, float, N * DSz);
+        ALLOC(D.V, float, N * DSz);
+        ALLOC(D.Xprev, float, N * DSz);
+        ALLOC(D.Gprev, float, N * DSz);
+        ALLOC(D.Pd, float, N * DSz);
+        ALLOC(D.Gh, float, N * DSz);
         ALLOC(D.ginf, float, N);
-        if (c->grad_mode == CHISAO_GRAD_FD) ALLOC(D.Gp, float, N * (size_t)c->M * d);
+        if (any_fd) ALLOC(D.Gp, float, N * (size_t)Mmax * DSz);
         ALLOC(D.stuck, uint8_t, N);
         ALLOC(D.active, uint8_t, N);
         ALLOC(D.conv, uint8_t, N);
@@ -226,41 +392,34 @@ extern "C" int chisao_init(chisao_handle *out, const chisao_problem *p, const ch
         ALLOC(D.status, uint8_t, N);
         ALLOC(D.reset, uint8_t, N);
         ALLOC(D.steep, uint8_t, N);
-        ALLOC(D.trace, uint8_t, N * (size_t)(D.n_conv + 1));
-        ALLOC(D.S, float, N * m * d);
-        ALLOC(D.Y, float, N * m * d);
-        ALLOC(D.rho, float, N * m);
+        ALLOC(D.trace, uint8_t, N * (size_t)(ncmax + 1));
+        ALLOC(D.S, float, N * (size_t)mmax * DSz);
+        ALLOC(D.Y, float, N * (size_t)mmax * DSz);
+        ALLOC(D.rho, float, N * (size_t)mmax);
         ALLOC(D.head, int, N);
         ALLOC(D.cnt, int, N);
         ALLOC(D.lists, int, N * kNumLists);
-        ALLOC(D.ctl, Ctl, 1);
-        ALLOC(D.records, CycleRecord, (size_t)c->n_osc);
-        ALLOC(D.part, double, (size_t)D.n_part_blocks * 129);
-
-        hipStream_t st = h->stream;
-        hipError_t e;
-#define HIP_GO(expr)                                                                              \
-    do {                                                                                          \
-        if ((e = (expr)) != hipSuccess) {                                                         \
-            rc = fail(CHISAO_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e));                    \
-            goto fail_out;                                                                        \
-        }                                                                                         \
-    } while (0)
-        HIP_GO(hipMemcpyAsync(lo, p->lo, sizeof(float) * d, hipMemcpyHostToDevice, st));
-        HIP_GO(hipMemcpyAsync(hi, p->hi, sizeof(float) * d, hipMemcpyHostToDevice, st));
-        HIP_GO(hipMemcpyAsync(tmp_w, p->log_w, sizeof(float) * K, hipMemcpyHostToDevice, st));
-        HIP_GO(hipMemcpyAsync(tmp_mu, p->mu, sizeof(float) * K * d, hipMemcpyHostToDevice, st));
-        HIP_GO(hipMemcpyAsync(tmp_prec, p->prec, sizeof(float) * K * d * d, hipMemcpyHostToDevice, st));
-        HIP_GO(hipMemsetAsync(bad, 0, sizeof(int), st));
-        HIP_GO(launch_prepare(D.family, D.d, D.DP, D.K, D.nu, tmp_w, tmp_mu, tmp_prec, logc2, Pfrag, muB, muC, bad, st));
-        // population and control state
-        if (x0_dev) HIP_GO(hipMemcpyAsync(D.X, x0_dev, sizeof(float) * N * d, hipMemcpyDeviceToDevice, st));
-        else HIP_GO(launch_uniform_init(D, st));
+        ALLOC(D.ctl, Ctl, P);
+        ALLOC(D.records, CycleRecord, P * (size_t)D.n_osc);
+        ALLOC(D.part, double, P * (size_t)D.n_part_blocks * 129);
+        ALLOC(D.prof, unsigned long long, kProfClasses);
+        HIP_GO(hipMemsetAsync(D.X, 0, sizeof(float) * N * DSz, st));
+        HIP_GO(launch_uniform_init(D, st));
+        if (x0_dev) {
+            for (int p = 0; p < n_problems; ++p)
+                if (x0_dev[p]) {
+                    const ProblemDesc &q = h->pdh[p];
+                    HIP_GO(hipMemcpy2DAsync(D.X + (size_t)q.s0 * DSz, DSz * sizeof(float), x0_dev[p],
+                                            (size_t)q.d * sizeof(float), (size_t)q.d * sizeof(float), (size_t)q.N,
+                                            hipMemcpyDeviceToDevice, st));
+                }
+        }
         HIP_GO(launch_fill_u8(D.active, 1, N, st));
         HIP_GO(launch_fill_u8(D.stuck, 0, N, st));
-        HIP_GO(hipMemsetAsync(D.V, 0, sizeof(float) * N * d, st));
-        HIP_GO(hipMemsetAsync(D.ctl, 0, sizeof(Ctl), st));
-        HIP_GO(hipMemsetAsync(D.records, 0, sizeof(CycleRecord) * c->n_osc, st));
+        HIP_GO(hipMemsetAsync(D.V, 0, sizeof(float) * N * DSz, st));
+        HIP_GO(hipMemsetAsync(D.ctl, 0, sizeof(Ctl) * P, st));
+        HIP_GO(hipMemsetAsync(D.records, 0, sizeof(CycleRecord) * P * D.n_osc, st));
+        HIP_GO(hipMemsetAsync(D.prof, 0, sizeof(unsigned long long) * kProfClasses, st));
         int bad_h = 0;
         HIP_GO(hipMemcpyAsync(&bad_h, bad, sizeof(int), hipMemcpyDeviceToHost, st));
         HIP_GO(hipStreamSynchronize(st));
@@ -269,25 +428,37 @@ extern "C" int chisao_init(chisao_handle *out, const chisao_problem *p, const ch
             goto fail_out;
         }
         if (x0_dev) {
-            // the starting population must lie in the box
-            std::vector<float> xh(N * d), loh(p->lo, p->lo + d), hih(p->hi, p->hi + d);
-            HIP_GO(hipMemcpy(xh.data(), D.X, sizeof(float) * N * d, hipMemcpyDeviceToHost));
-            for (size_t i = 0; i < N * d; ++i) {
-                const size_t j = i % d;
-                if (!(xh[i] >= loh[j] && xh[i] <= hih[j])) {
-                    rc = fail(CHISAO_E_INVAL, "x0 sample %zu lies outside the box", i / d);
-                    goto fail_out;
+            // starting populations must lie in their boxes
+            for (int p = 0; p < n_problems; ++p) {
+                if (!x0_dev[p]) continue;
+                const ProblemDesc &q = h->pdh[p];
+                std::vector<float> xh((size_t)q.N * q.d);
+                HIP_GO(hipMemcpy(xh.data(), x0_dev[p], sizeof(float) * xh.size(), hipMemcpyDeviceToHost));
+                for (size_t i = 0; i < xh.size(); ++i) {
+                    const size_t j = i % q.d;
+                    if (!(xh[i] >= ps[p].lo[j] && xh[i] <= ps[p].hi[j])) {
+                        rc = fail(CHISAO_E_INVAL, "problem %d: x0 sample %zu lies outside the box", p, i / q.d);
+                        goto fail_out;
+                    }
                 }
             }
         }
+        HIP_GO(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
     }
 #undef ALLOC
 #undef HIP_GO
     *out = h;
     return CHISAO_OK;
 fail_out:
+    (void)hipStreamSynchronize(h->stream);
     delete h;
     return rc;
+}
+
+extern "C" int chisao_init(chisao_handle *out, const chisao_problem *p, const chisao_config *c, const float *x0_dev,
+                           void *hip_stream) {
+    const float *x0s[1] = {x0_dev};
+    return chisao_init_batched(out, 1, p, c, x0_dev ? x0s : nullptr, hip_stream);
 }
 
 extern "C" void chisao_destroy(chisao_handle h) {
@@ -299,119 +470,148 @@ extern "C" void chisao_destroy(chisao_handle h) {
 // ---------------------------------------------------------------------------
 // Phase sequences
 // ---------------------------------------------------------------------------
-static int eval_args_base(chisao_ctx *h, EvalArgs &a) {
+static EvalArgs base_args(chisao_ctx *h, const EvalClass &c) {
+    EvalArgs a;
     memset(&a, 0, sizeof a);
     a.D = h->D;
+    a.cls = c.pids_dev;
+    a.n_cls = (int)c.pids.size();
     a.X = h->D.X;
-    a.Vc = 1;
+    a.x_stride = h->D.DS;
+    a.out_stride = h->D.DS;
+    a.ext_n = -1;
+    a.list_id = -1;
     a.trial_next = -1;
-    return 0;
+    return a;
 }
 
-static inline int *host_list(const Dev &D, int id) { return D.lists + (size_t)id * D.N; }
+// Upper bound on the tiles of a launch (sizes its grid).
+static long tile_bound(chisao_ctx *h, const EvalClass &c, int vc_kind, bool fd) {
+    long t = 0;
+    for (int p : c.pids) {
+        const ProblemDesc &q = h->pdh[p];
+        const int Vc = vc_kind == kVcTrialRest ? q.ls_max - 1 : (vc_kind == kVcProbes ? q.M : 1);
+        const long V = (long)Vc * (fd ? 2 * q.d : 1);
+        if (V <= 0) continue;
+        t += V <= 32 ? (q.N + (32 / V) - 1) / (32 / V) : (long)q.N * ((V + 31) / 32);
+    }
+    return t;
+}
 
-static hipError_t run_eval(chisao_ctx *h, const EvalArgs &a, int center, bool fd, bool grad) {
+static hipError_t run_eval(chisao_ctx *h, const EvalClass &c, EvalArgs &a, int center, bool fd, bool grad) {
+    a.max_tiles = tile_bound(h, c, a.vc_kind, fd);
     const int cls = fd ? CHISAO_PROF_EVAL_FD : center;
-    return timed(h, cls, [&] { return launch_eval(a, center, fd, grad, h->stream); });
+    return timed(h, cls, [&] { return launch_eval(a, c.DP, c.family, center, fd, grad, h->cur); });
 }
 
-static hipError_t eval_list(chisao_ctx *h, int list_id, float *F_out, float *G_out, bool want_f) {
-    const Dev &D = h->D;
-    hipStream_t st = h->stream;
-    EvalArgs a;
-    eval_args_base(h, a);
-    a.list = host_list(D, list_id);
-    a.count_ptr = &D.ctl->count[list_id];
-    a.n_jobs = D.N;
-    if (D.grad_mode == CHISAO_GRAD_ADJOINT) {
-        a.F_out = F_out;
+// value and gradient of the samples on a list: adjoint in one pass; with
+// finite differences the value (if wanted) and the stencil gradient
+static hipError_t eval_list(chisao_ctx *h, int list_id, float *F_out, float *G_out, bool want_f, int need_bit,
+                            int step_limit, int step) {
+    for (const EvalClass &c : h->eclasses) {
+        EvalArgs a = base_args(h, c);
+        a.list_id = list_id;
+        a.vc_kind = kVcOne;
+        a.need_bit = need_bit;
+        a.step_limit = step_limit;
+        a.step = step;
+        hipError_t e;
+        if (c.grad_mode == CHISAO_GRAD_ADJOINT) {
+            a.F_out = F_out;
+            a.G_out = G_out;
+            if ((e = run_eval(h, c, a, kDirect, false, true)) != hipSuccess) return e;
+            continue;
+        }
+        if (want_f) {
+            a.F_out = F_out;
+            a.G_out = nullptr;
+            if ((e = run_eval(h, c, a, kDirect, false, false)) != hipSuccess) return e;
+        }
+        a.F_out = nullptr;
         a.G_out = G_out;
-        return run_eval(h, a, kDirect, false, true);
+        if ((e = run_eval(h, c, a, kDirect, true, false)) != hipSuccess) return e;
     }
-    hipError_t e = hipSuccess;
-    if (want_f) {
-        a.F_out = F_out;
-        a.G_out = nullptr;
-        e = run_eval(h, a, kDirect, false, false);
-        if (e != hipSuccess) return e;
-    }
-    a.F_out = nullptr;
-    a.G_out = G_out;
-    return run_eval(h, a, kDirect, true, false);
+    return hipSuccess;
 }
 
 static hipError_t phase_converge(chisao_ctx *h) {
     const Dev &D = h->D;
-    hipStream_t st = h->stream;
+    hipStream_t st = h->cur;
     hipError_t e;
-    const bool adj = D.grad_mode == CHISAO_GRAD_ADJOINT;
     if ((e = launch_begin_cycle(D, st)) != hipSuccess) return e;
-    if ((e = eval_list(h, L_ACT, D.F, D.G, true)) != hipSuccess) return e;
-    for (int t = 1; t <= D.n_conv + 1; ++t) {
+    if ((e = eval_list(h, L_ACT, D.F, D.G, true, 0, 0, 0)) != hipSuccess) return e;
+    for (int t = 1; t <= D.n_conv_max + 1; ++t) {
         if ((e = launch_reset_counts(D, (1 << L_T1) | (1 << L_T2) | (1 << L_FD), st)) != hipSuccess) return e;
-        if ((e = timed(h, CHISAO_PROF_LBFGS, [&] { return launch_lbfgs_step(D, t, st); })) != hipSuccess) return e;
-        if (t > D.n_conv) break;
-        EvalArgs a;
-        eval_args_base(h, a);
-        a.list = host_list(D, L_T1);
-        a.count_ptr = &D.ctl->count[L_T1];
-        a.n_jobs = D.N;
-        a.Vc = 1;
-        a.r0 = 0;
-        a.trial_next = D.ls_max > 1 ? L_T2 : -1;
-        if ((e = run_eval(h, a, kTrial, false, adj)) != hipSuccess) return e;
-        if (D.ls_max > 1) {
-            a.list = host_list(D, L_T2);
-            a.count_ptr = &D.ctl->count[L_T2];
-            a.Vc = D.ls_max - 1;
-            a.r0 = 1;
-            a.trial_next = -1;
-            if ((e = run_eval(h, a, kTrial, false, adj)) != hipSuccess) return e;
+        for (const LbfgsClass &lc : h->lclasses)
+            if ((e = timed(h, CHISAO_PROF_LBFGS,
+                           [&] { return launch_lbfgs_step(D, t, lc.cpl, lc.samples_dev, lc.n, st); })) != hipSuccess)
+                return e;
+        if (t > D.n_conv_max) break;
+        for (const EvalClass &c : h->eclasses) {
+            const bool adj = c.grad_mode == CHISAO_GRAD_ADJOINT;
+            EvalArgs a = base_args(h, c);
+            a.list_id = L_T1;
+            a.vc_kind = kVcTrialFirst;
+            a.trial_next = L_T2;
+            if ((e = run_eval(h, c, a, kTrial, false, adj)) != hipSuccess) return e;
         }
-        if (!adj) {
-            EvalArgs b;
-            eval_args_base(h, b);
-            b.list = host_list(D, L_FD);
-            b.count_ptr = &D.ctl->count[L_FD];
-            b.n_jobs = D.N;
-            b.G_out = D.G;
-            if ((e = run_eval(h, b, kDirect, true, false)) != hipSuccess) return e;
+        for (const EvalClass &c : h->eclasses) {
+            const bool adj = c.grad_mode == CHISAO_GRAD_ADJOINT;
+            EvalArgs a = base_args(h, c);
+            a.list_id = L_T2;
+            a.vc_kind = kVcTrialRest;
+            a.trial_next = -1;
+            if ((e = run_eval(h, c, a, kTrial, false, adj)) != hipSuccess) return e;
+            if (!adj) {
+                EvalArgs b = base_args(h, c);
+                b.list_id = L_FD;
+                b.vc_kind = kVcOne;
+                b.G_out = D.G;
+                if ((e = run_eval(h, c, b, kDirect, true, false)) != hipSuccess) return e;
+            }
         }
     }
     return hipSuccess;
 }
 
+static int max_over(chisao_ctx *h, int ProblemDesc::*f) {
+    int v = 0;
+    for (const ProblemDesc &q : h->pdh) v = std::max(v, q.*f);
+    return v;
+}
+
 static hipError_t phase_hlc(chisao_ctx *h) {
     const Dev &D = h->D;
-    hipStream_t st = h->stream;
+    hipStream_t st = h->cur;
     hipError_t e;
-    if ((e = launch_build_list(D, L_UNF, st)) != hipSuccess) return e;
+    if ((e = launch_build_unfrozen(D, st)) != hipSuccess) return e;
     if ((e = launch_sigma(D, st)) != hipSuccess) return e;
-    if (!((D.phase_mask >> 5) & 1)) return hipSuccess;
-    const bool adj = D.grad_mode == CHISAO_GRAD_ADJOINT;
-    for (int step = 0; step < D.n_cloud; ++step) {
-        EvalArgs a;
-        eval_args_base(h, a);
-        a.list = host_list(D, L_UNF);
-        a.count_ptr = &D.ctl->count[L_UNF];
-        a.n_jobs = D.N;
-        a.Vc = D.M;
-        a.step = step;
-        if ((e = run_eval(h, a, kProbe, !adj, adj)) != hipSuccess) return e;
-        if (!adj && (e = launch_probe_mean(D, st)) != hipSuccess) return e;
+    const int n_cloud = max_over(h, &ProblemDesc::n_cloud);
+    for (int step = 0; step < n_cloud; ++step) {
+        for (const EvalClass &c : h->eclasses) {
+            const bool adj = c.grad_mode == CHISAO_GRAD_ADJOINT;
+            EvalArgs a = base_args(h, c);
+            a.list_id = L_UNF;
+            a.vc_kind = kVcProbes;
+            a.step = step;
+            a.need_bit = 1 << 5;
+            a.step_limit = 1;
+            if ((e = run_eval(h, c, a, kProbe, !adj, adj)) != hipSuccess) return e;
+        }
+        if ((e = launch_probe_mean(D, step, st)) != hipSuccess) return e;
         if (step == 0 && (e = launch_step_size(D, D.Gh, 0, st)) != hipSuccess) return e;
-        if ((e = launch_hlc_update(D, st)) != hipSuccess) return e;
+        if ((e = launch_hlc_update(D, step, st)) != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
 static hipError_t phase_anti(chisao_ctx *h) {
     const Dev &D = h->D;
-    hipStream_t st = h->stream;
+    hipStream_t st = h->cur;
     hipError_t e;
-    if (!((D.phase_mask >> 6) & 1)) return hipSuccess;
-    for (int step = 0; step < D.n_anti; ++step) {
-        if ((e = eval_list(h, L_UNF, nullptr, D.Gh, false)) != hipSuccess) return e;
+    const int n_anti = max_over(h, &ProblemDesc::n_anti);
+    for (int step = 0; step < n_anti; ++step) {
+        if ((e = eval_list(h, L_UNF, nullptr, D.Gh, false, 1 << 6, 2, step)) != hipSuccess) return e;
         if (step == 0 && (e = launch_step_size(D, D.Gh, 1, st)) != hipSuccess) return e;
         if ((e = launch_anti_update(D, step, st)) != hipSuccess) return e;
     }
@@ -421,7 +621,7 @@ static hipError_t phase_anti(chisao_ctx *h) {
 static hipError_t enqueue_phases(chisao_ctx *h, uint32_t mask) {
     hipError_t e;
     const Dev &D = h->D;
-    hipStream_t st = h->stream;
+    hipStream_t st = h->cur;
     if (mask & (1u << 1))
         if ((e = phase_converge(h)) != hipSuccess) return e;
     if (mask & (1u << 2))
@@ -437,9 +637,34 @@ static hipError_t enqueue_phases(chisao_ctx *h, uint32_t mask) {
     return hipSuccess;
 }
 
+static hipError_t enqueue_cycle(chisao_ctx *h, bool last) {
+    hipError_t e = enqueue_phases(h, last ? 0x0Eu : 0x7Eu);
+    if (e != hipSuccess) return e;
+    return launch_end_cycle(h->D, 1, h->cur);
+}
+
+// Capture one cycle (the kernels read every varying quantity, including the
+// cycle index, from device memory) and instantiate it.
+static int capture_cycle(chisao_ctx *h, bool last, hipGraphExec_t *out) {
+    hipGraph_t g = nullptr;
+    h->cur = h->cap;
+    hipError_t e = hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t e2 = enqueue_cycle(h, last);
+        e = hipStreamEndCapture(h->cap, &g);
+        if (e2 != hipSuccess) e = e2;
+    }
+    h->cur = h->stream;
+    if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(CHISAO_E_DEVICE, "graph capture of a cycle failed: %s", hipGetErrorString(e));
+    return CHISAO_OK;
+}
+
 extern "C" int chisao_run_phases(chisao_handle h, uint32_t phase_mask) {
     if (!h) return fail(CHISAO_E_INVAL, "null handle");
     HIP_TRY(hipSetDevice(h->device));
+    h->cur = h->stream;
     HIP_TRY(enqueue_phases(h, phase_mask & 0x7E));
     HIP_TRY(hipStreamSynchronize(h->stream));
     return CHISAO_OK;
@@ -453,63 +678,101 @@ extern "C" int chisao_cycle(chisao_handle h, int n_cycles, chisao_cycle_stats *s
                     h->D.n_osc - h->k_host, h->D.n_osc);
     HIP_TRY(hipSetDevice(h->device));
     const int k0 = h->k_host;
+    const bool graphs = !(h->flags & CHISAO_FLAG_NO_GRAPH) && !h->prof;
     for (int i = 0; i < n_cycles; ++i) {
         const bool last = (h->k_host + 1 == h->D.n_osc);
-        const uint32_t mask = last ? 0x0Eu : 0x7Eu;
-        HIP_TRY(enqueue_phases(h, mask));
-        HIP_TRY(launch_end_cycle(h->D, 1, h->stream));
+        if (graphs) {
+            hipGraphExec_t &g = h->graph[last ? 1 : 0];
+            if (!g) {
+                int rc = capture_cycle(h, last, &g);
+                if (rc) return rc;
+            }
+            HIP_TRY(hipGraphLaunch(g, h->stream));
+        } else {
+            h->cur = h->stream;
+            HIP_TRY(enqueue_cycle(h, last));
+        }
         h->k_host += 1;
     }
     if (stats_host && n_cycles > 0) {
-        std::vector<CycleRecord> rec(n_cycles);
-        HIP_TRY(hipMemcpyAsync(rec.data(), h->D.records + k0, sizeof(CycleRecord) * n_cycles,
-                               hipMemcpyDeviceToHost, h->stream));
+        const int P = h->D.P;
+        std::vector<CycleRecord> rec((size_t)P * h->D.n_osc);
+        HIP_TRY(hipMemcpyAsync(rec.data(), h->D.records, sizeof(CycleRecord) * rec.size(), hipMemcpyDeviceToHost,
+                               h->stream));
         HIP_TRY(hipStreamSynchronize(h->stream));
-        for (int i = 0; i < n_cycles; ++i) {
-            chisao_cycle_stats &o = stats_host[i];
-            const CycleRecord &r = rec[i];
-            o.k = r.k;
-            o.f_max = r.f_max;
-            o.n_stuck = r.n_stuck;
-            o.K_lost = r.K_lost;
-            o.n_modes = r.n_modes;
-            o.reseed_kind = r.reseed_kind;
-            o.n_free = r.n_free;
-            o.n_unfrozen = r.n_unfrozen;
-            o.n_active = r.n_active;
-            o.sigma = r.sigma;
-            o.alpha_c = r.alpha_c;
-            o.alpha_a = r.alpha_a;
-            o.ls_fail = r.ls_fail;
-            o.evals = r.evals;
-        }
+        for (int i = 0; i < n_cycles; ++i)
+            for (int p = 0; p < P; ++p) {
+                chisao_cycle_stats &o = stats_host[(size_t)i * P + p];
+                const CycleRecord &r = rec[(size_t)p * h->D.n_osc + k0 + i];
+                o.k = r.k;
+                o.f_max = r.f_max;
+                o.n_stuck = r.n_stuck;
+                o.K_lost = r.K_lost;
+                o.n_modes = r.n_modes;
+                o.reseed_kind = r.reseed_kind;
+                o.n_free = r.n_free;
+                o.n_unfrozen = r.n_unfrozen;
+                o.n_active = r.n_active;
+                o.sigma = r.sigma;
+                o.alpha_c = r.alpha_c;
+                o.alpha_a = r.alpha_a;
+                o.ls_fail = r.ls_fail;
+                o.evals = r.evals;
+            }
     }
     return CHISAO_OK;
 }
 
-extern "C" int chisao_get_state(chisao_handle h, chisao_state *s) {
+// ---------------------------------------------------------------------------
+// State, modes, evaluation, profiling
+// ---------------------------------------------------------------------------
+static int check_problem(chisao_ctx *h, int p) {
+    if (p < 0 || p >= h->D.P) return fail(CHISAO_E_INVAL, "problem index %d out of range", p);
+    return CHISAO_OK;
+}
+
+// rows [s0, s0+N) of a stride-DS device array to a dense host array of stride w
+static hipError_t rows_d2h(void *dst, const void *src, size_t elem, size_t w, size_t DS, size_t s0, size_t N) {
+    return hipMemcpy2D(dst, w * elem, (const char *)src + s0 * DS * elem, DS * elem, w * elem, N,
+                       hipMemcpyDeviceToHost);
+}
+
+extern "C" int chisao_get_state(chisao_handle h, int problem, chisao_state *s) {
     if (!h || !s) return fail(CHISAO_E_INVAL, "null argument");
+    int rc = check_problem(h, problem);
+    if (rc) return rc;
     const Dev &D = h->D;
-    const size_t N = D.N, d = D.d;
+    const ProblemDesc &q = h->pdh[problem];
+    const size_t N = q.N, d = q.d, DS = D.DS, s0 = q.s0, m = q.m, mx = D.mmax;
     HIP_TRY(hipSetDevice(h->device));
     HIP_TRY(hipStreamSynchronize(h->stream));
-    if (s->X) HIP_TRY(hipMemcpy(s->X, D.X, sizeof(float) * N * d, hipMemcpyDeviceToHost));
-    if (s->F) HIP_TRY(hipMemcpy(s->F, D.F, sizeof(float) * N, hipMemcpyDeviceToHost));
-    if (s->G) HIP_TRY(hipMemcpy(s->G, D.G, sizeof(float) * N * d, hipMemcpyDeviceToHost));
-    if (s->stuck) HIP_TRY(hipMemcpy(s->stuck, D.stuck, N, hipMemcpyDeviceToHost));
-    if (s->active) HIP_TRY(hipMemcpy(s->active, D.active, N, hipMemcpyDeviceToHost));
-    if (s->stuck_pre) HIP_TRY(hipMemcpy(s->stuck_pre, D.stuck_pre, N, hipMemcpyDeviceToHost));
-    if (s->removed) HIP_TRY(hipMemcpy(s->removed, D.removed, N, hipMemcpyDeviceToHost));
-    if (s->trace) HIP_TRY(hipMemcpy(s->trace, D.trace, N * (size_t)(D.n_conv + 1), hipMemcpyDeviceToHost));
-    const size_t m = D.m;
-    if (s->S) HIP_TRY(hipMemcpy(s->S, D.S, sizeof(float) * N * m * d, hipMemcpyDeviceToHost));
-    if (s->Y) HIP_TRY(hipMemcpy(s->Y, D.Y, sizeof(float) * N * m * d, hipMemcpyDeviceToHost));
-    if (s->rho) HIP_TRY(hipMemcpy(s->rho, D.rho, sizeof(float) * N * m, hipMemcpyDeviceToHost));
-    if (s->head) HIP_TRY(hipMemcpy(s->head, D.head, sizeof(int) * N, hipMemcpyDeviceToHost));
-    if (s->cnt) HIP_TRY(hipMemcpy(s->cnt, D.cnt, sizeof(int) * N, hipMemcpyDeviceToHost));
-    if (s->conv) HIP_TRY(hipMemcpy(s->conv, D.conv, N, hipMemcpyDeviceToHost));
+    if (s->X) HIP_TRY(rows_d2h(s->X, D.X, 4, d, DS, s0, N));
+    if (s->F) HIP_TRY(hipMemcpy(s->F, D.F + s0, sizeof(float) * N, hipMemcpyDeviceToHost));
+    if (s->G) HIP_TRY(rows_d2h(s->G, D.G, 4, d, DS, s0, N));
+    if (s->stuck) HIP_TRY(hipMemcpy(s->stuck, D.stuck + s0, N, hipMemcpyDeviceToHost));
+    if (s->active) HIP_TRY(hipMemcpy(s->active, D.active + s0, N, hipMemcpyDeviceToHost));
+    if (s->stuck_pre) HIP_TRY(hipMemcpy(s->stuck_pre, D.stuck_pre + s0, N, hipMemcpyDeviceToHost));
+    if (s->removed) HIP_TRY(hipMemcpy(s->removed, D.removed + s0, N, hipMemcpyDeviceToHost));
+    if (s->trace)
+        HIP_TRY(hipMemcpy2D(s->trace, N, D.trace + s0, (size_t)D.NT, N, (size_t)q.n_conv + 1, hipMemcpyDeviceToHost));
+    if (s->S || s->Y) {
+        std::vector<float> tmp(N * mx * DS);
+        for (int which = 0; which < 2; ++which) {
+            float *dst = which ? s->Y : s->S;
+            if (!dst) continue;
+            HIP_TRY(hipMemcpy(tmp.data(), (which ? D.Y : D.S) + s0 * mx * DS, sizeof(float) * tmp.size(),
+                              hipMemcpyDeviceToHost));
+            for (size_t i = 0; i < N; ++i)
+                for (size_t j = 0; j < m; ++j)
+                    memcpy(dst + (i * m + j) * d, tmp.data() + (i * mx + j) * DS, sizeof(float) * d);
+        }
+    }
+    if (s->rho) HIP_TRY(rows_d2h(s->rho, D.rho, 4, m, mx, s0, N));
+    if (s->head) HIP_TRY(hipMemcpy(s->head, D.head + s0, sizeof(int) * N, hipMemcpyDeviceToHost));
+    if (s->cnt) HIP_TRY(hipMemcpy(s->cnt, D.cnt + s0, sizeof(int) * N, hipMemcpyDeviceToHost));
+    if (s->conv) HIP_TRY(hipMemcpy(s->conv, D.conv + s0, N, hipMemcpyDeviceToHost));
     Ctl c;
-    HIP_TRY(hipMemcpy(&c, D.ctl, sizeof c, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(&c, D.ctl + problem, sizeof c, hipMemcpyDeviceToHost));
     s->k = c.k;
     s->gr_disabled = c.gr_disabled;
     s->gr_fail = c.gr_fail;
@@ -518,54 +781,107 @@ extern "C" int chisao_get_state(chisao_handle h, chisao_state *s) {
     return CHISAO_OK;
 }
 
-extern "C" int chisao_set_state(chisao_handle h, const chisao_state *s) {
+extern "C" int chisao_set_state(chisao_handle h, int problem, const chisao_state *s) {
     if (!h || !s) return fail(CHISAO_E_INVAL, "null argument");
+    int rc = check_problem(h, problem);
+    if (rc) return rc;
     const Dev &D = h->D;
-    const size_t N = D.N, d = D.d;
+    const ProblemDesc &q = h->pdh[problem];
+    const size_t N = q.N, d = q.d, DS = D.DS, s0 = q.s0;
     if (s->k < 0 || s->k > D.n_osc) return fail(CHISAO_E_INVAL, "k out of range");
+    if (h->D.P > 1 && s->k != h->k_host) return fail(CHISAO_E_INVAL, "a batch keeps one cycle count for all problems");
     HIP_TRY(hipSetDevice(h->device));
     HIP_TRY(hipStreamSynchronize(h->stream));
     if (s->X) {
         std::vector<float> lo(d), hi(d);
-        HIP_TRY(hipMemcpy(lo.data(), D.lo, sizeof(float) * d, hipMemcpyDeviceToHost));
-        HIP_TRY(hipMemcpy(hi.data(), D.hi, sizeof(float) * d, hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(lo.data(), q.lo, sizeof(float) * d, hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(hi.data(), q.hi, sizeof(float) * d, hipMemcpyDeviceToHost));
         for (size_t i = 0; i < N * d; ++i)
             if (!(s->X[i] >= lo[i % d] && s->X[i] <= hi[i % d]))
                 return fail(CHISAO_E_INVAL, "sample %zu lies outside the box", i / d);
-        HIP_TRY(hipMemcpy(D.X, s->X, sizeof(float) * N * d, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy2D(D.X + s0 * DS, DS * 4, s->X, d * 4, d * 4, N, hipMemcpyHostToDevice));
     }
-    if (s->stuck) HIP_TRY(hipMemcpy(D.stuck, s->stuck, N, hipMemcpyHostToDevice));
-    if (s->active) HIP_TRY(hipMemcpy(D.active, s->active, N, hipMemcpyHostToDevice));
+    if (s->stuck) HIP_TRY(hipMemcpy(D.stuck + s0, s->stuck, N, hipMemcpyHostToDevice));
+    if (s->active) HIP_TRY(hipMemcpy(D.active + s0, s->active, N, hipMemcpyHostToDevice));
     Ctl c;
-    HIP_TRY(hipMemcpy(&c, D.ctl, sizeof c, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(&c, D.ctl + problem, sizeof c, hipMemcpyDeviceToHost));
     c.k = s->k;
     c.gr_disabled = s->gr_disabled;
     c.gr_fail = s->gr_fail;
     c.gr_used_last = s->gr_used_last;
     c.gr_prev_modes = s->gr_prev_modes;
-    HIP_TRY(hipMemcpy(D.ctl, &c, sizeof c, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(D.ctl + problem, &c, sizeof c, hipMemcpyHostToDevice));
     h->k_host = s->k;
     return CHISAO_OK;
 }
 
 extern "C" int chisao_modes(chisao_handle h, int problem, float *x_out, float *f_out, int cap, int *n_out) {
     if (!h || !n_out) return fail(CHISAO_E_INVAL, "null argument");
-    if (problem != 0) return fail(CHISAO_E_INVAL, "single-problem handle: problem must be 0");
+    int rc = check_problem(h, problem);
+    if (rc) return rc;
     const Dev &D = h->D;
+    const ProblemDesc &q = h->pdh[problem];
     HIP_TRY(hipSetDevice(h->device));
-    HIP_TRY(launch_mode_list(D, h->stream));
+    HIP_TRY(launch_mode_list(D, problem, q.s0, q.N, h->stream));
     Ctl c;
-    HIP_TRY(hipMemcpyAsync(&c, D.ctl, sizeof c, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipMemcpyAsync(&c, D.ctl + problem, sizeof c, hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
     const int n = c.count[O_PEAKS];
     *n_out = n;
     if (cap < n) return fail(CHISAO_E_RANGE, "capacity %d < %d modes", cap, n);
     if (n == 0) return CHISAO_OK;
     if (!x_out) return fail(CHISAO_E_INVAL, "null x_out");
-    // rows gathered into Gh (scratch at this point), values into Pd
-    HIP_TRY(hipMemcpyAsync(x_out, D.Gh, sizeof(float) * (size_t)n * D.d, hipMemcpyDeviceToHost, h->stream));
-    if (f_out) HIP_TRY(hipMemcpyAsync(f_out, D.Pd, sizeof(float) * (size_t)n, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipMemcpyAsync(x_out, D.Gh + (size_t)q.s0 * D.DS, sizeof(float) * (size_t)n * q.d, hipMemcpyDeviceToHost,
+                           h->stream));
+    if (f_out) HIP_TRY(hipMemcpyAsync(f_out, D.Pd + q.s0, sizeof(float) * (size_t)n, hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
+    return CHISAO_OK;
+}
+
+extern "C" int chisao_eval(chisao_handle h, int problem, const float *X_dev, int B, float *f_dev, float *G_dev,
+                           int grad_mode) {
+    if (!h) return fail(CHISAO_E_INVAL, "null handle");
+    int rc = check_problem(h, problem);
+    if (rc) return rc;
+    if (B < 0) return fail(CHISAO_E_INVAL, "negative batch");
+    if (grad_mode != CHISAO_GRAD_FD && grad_mode != CHISAO_GRAD_ADJOINT) return fail(CHISAO_E_INVAL, "bad grad_mode");
+    if (B == 0) return CHISAO_OK;
+    if (!X_dev) return fail(CHISAO_E_INVAL, "null X");
+    HIP_TRY(hipSetDevice(h->device));
+    const ProblemDesc &q = h->pdh[problem];
+    EvalClass c;
+    c.DP = q.DP;
+    c.family = q.family;
+    c.grad_mode = grad_mode;
+    c.pids = {problem};
+    c.pids_dev = h->pid_seq + problem;
+    EvalArgs a = base_args(h, c);
+    a.X = X_dev;
+    a.x_stride = q.d;
+    a.out_stride = q.d;
+    a.ext_n = B;
+    a.vc_kind = kVcOne;
+    const long Vfd = 2 * q.d;
+    hipStream_t st = h->stream;
+    if (grad_mode == CHISAO_GRAD_ADJOINT) {
+        a.F_out = f_dev;
+        a.G_out = G_dev;
+        a.max_tiles = (B + 31) / 32;
+        HIP_TRY(launch_eval(a, q.DP, q.family, kDirect, false, G_dev != nullptr, st));
+        return CHISAO_OK;
+    }
+    if (f_dev) {
+        a.F_out = f_dev;
+        a.G_out = nullptr;
+        a.max_tiles = (B + 31) / 32;
+        HIP_TRY(launch_eval(a, q.DP, q.family, kDirect, false, false, st));
+    }
+    if (G_dev) {
+        a.F_out = nullptr;
+        a.G_out = G_dev;
+        a.max_tiles = Vfd <= 32 ? (B + (32 / Vfd) - 1) / (32 / Vfd) : (long)B * ((Vfd + 31) / 32);
+        HIP_TRY(launch_eval(a, q.DP, q.family, kDirect, true, false, st));
+    }
     return CHISAO_OK;
 }
 
@@ -574,8 +890,8 @@ extern "C" int chisao_profile(chisao_handle h, int enable, chisao_kernel_profile
     HIP_TRY(hipSetDevice(h->device));
     if (enable) {
         HIP_TRY(hipStreamSynchronize(h->stream));
-        unsigned long long zero[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        HIP_TRY(hipMemcpy(h->D.ctl->prof_points, zero, sizeof zero, hipMemcpyHostToDevice));
+        unsigned long long zero[kProfClasses] = {};
+        HIP_TRY(hipMemcpy(h->D.prof, zero, sizeof zero, hipMemcpyHostToDevice));
         h->ev_used.clear();
         h->prof = true;
         return CHISAO_OK;
@@ -591,44 +907,11 @@ extern "C" int chisao_profile(chisao_handle h, int enable, chisao_kernel_profile
             res[u.first].launches += 1;
             res[u.first].ms += ms;
         }
-        unsigned long long pts[8];
-        HIP_TRY(hipMemcpy(pts, h->D.ctl->prof_points, sizeof pts, hipMemcpyDeviceToHost));
-        for (int i = 0; i < 8 && i < CHISAO_PROF_CLASSES; ++i) res[i].points = (int64_t)pts[i];
+        unsigned long long pts[kProfClasses];
+        HIP_TRY(hipMemcpy(pts, h->D.prof, sizeof pts, hipMemcpyDeviceToHost));
+        for (int i = 0; i < kProfClasses && i < CHISAO_PROF_CLASSES; ++i) res[i].points = (int64_t)pts[i];
         memcpy(out, res, sizeof res);
     }
     h->ev_used.clear();
-    return CHISAO_OK;
-}
-
-extern "C" int chisao_eval(chisao_handle h, const float *X_dev, int B, float *f_dev, float *G_dev, int grad_mode) {
-    if (!h) return fail(CHISAO_E_INVAL, "null handle");
-    if (B < 0) return fail(CHISAO_E_INVAL, "negative batch");
-    if (B == 0) return CHISAO_OK;
-    if (!X_dev) return fail(CHISAO_E_INVAL, "null X");
-    if (grad_mode != CHISAO_GRAD_FD && grad_mode != CHISAO_GRAD_ADJOINT) return fail(CHISAO_E_INVAL, "bad grad_mode");
-    HIP_TRY(hipSetDevice(h->device));
-    EvalArgs a;
-    eval_args_base(h, a);
-    a.X = X_dev;
-    a.list = nullptr;
-    a.count_ptr = nullptr;
-    a.n_jobs = B;
-    hipStream_t st = h->stream;
-    if (grad_mode == CHISAO_GRAD_ADJOINT) {
-        a.F_out = f_dev;
-        a.G_out = G_dev;
-        HIP_TRY(launch_eval(a, kDirect, false, G_dev != nullptr, st));
-        return CHISAO_OK;
-    }
-    if (f_dev) {
-        a.F_out = f_dev;
-        a.G_out = nullptr;
-        HIP_TRY(launch_eval(a, kDirect, false, false, st));
-    }
-    if (G_dev) {
-        a.F_out = nullptr;
-        a.G_out = G_dev;
-        HIP_TRY(launch_eval(a, kDirect, true, false, st));
-    }
     return CHISAO_OK;
 }

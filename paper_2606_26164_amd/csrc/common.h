@@ -73,6 +73,29 @@ __device__ __forceinline__ float wave_min(float v) {
     return v;
 }
 
+// Reductions over the 16 lanes of a DPP row (lanes 16r .. 16r+15), with
+// every lane of the row receiving the same, bitwise identical result:
+// quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror, row_mirror.
+// All 64 lanes must be active.
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float row16_sum(float v) {
+    v += dpp_mov<0xB1>(v);
+    v += dpp_mov<0x4E>(v);
+    v += dpp_mov<0x141>(v);
+    v += dpp_mov<0x140>(v);
+    return v;
+}
+__device__ __forceinline__ float row16_max(float v) {
+    v = fmaxf(v, dpp_mov<0xB1>(v));
+    v = fmaxf(v, dpp_mov<0x4E>(v));
+    v = fmaxf(v, dpp_mov<0x141>(v));
+    v = fmaxf(v, dpp_mov<0x140>(v));
+    return v;
+}
+
 // Total order on floats as signed ints, for exact atomic max.
 __device__ __forceinline__ int float_to_ordered(float f) {
     int i = __float_as_int(f);
@@ -89,8 +112,27 @@ __host__ __device__ inline float ordered_to_float(int i) {
 }
 
 // ---------------------------------------------------------------------------
-// Device control block: counters and scalars that decide the data-dependent
-// control flow of a cycle without a host round trip.
+// Problems.  A handle holds P independent problems; problem p owns the global
+// samples [s0, s0 + N).  All per-sample arrays are concatenated, rows have
+// the handle-wide stride DS >= d.
+// ---------------------------------------------------------------------------
+struct ProblemDesc {
+    int d, DP, K, family;
+    float nu, nu_plus_d;
+    const float *Pfrag;  // [K][DP/4][64][DP/16] MFMA A-operand fragments of the precision matrices
+    const float *muB;    // [K][4][DP/4]  centre coordinates in B-operand lane order
+    const float *muC;    // [K][4][DP/4]  centre coordinates in accumulator lane order
+    const float *logc2;  // [K] log2 of weight times normaliser
+    const float *lo, *hi;
+    int N, s0;
+    int m, n_conv, n_anti, n_cloud, M, ls_max, grad_mode;
+    float eps_grad, eps_dup, log_delta, momentum, alpha, sigma_cfg, sigma_c, fd_h, ls_c1, curv_eps;
+    uint32_t key0, key1, phase_mask;
+};
+
+// ---------------------------------------------------------------------------
+// Per-problem control block: counters and scalars that decide the
+// data-dependent control flow of a cycle without a host round trip.
 // ---------------------------------------------------------------------------
 enum ListId { L_ACT = 0, L_T1, L_T2, L_FD, L_UNF, L_STK, O_SLOTS, O_FREE, O_PEAKS, kNumLists };
 
@@ -104,7 +146,6 @@ struct Ctl {
     int ls_fail;
     int evals;
     float f_max, sigma, alpha_c, alpha_a;
-    unsigned long long prof_points[8];  // cumulative evaluations per kernel class (profiling)
 };
 
 // Per-cycle record kept on the device, copied out on request.
@@ -127,32 +168,26 @@ constexpr uint8_t kTrStored = 0x10;
 constexpr uint8_t kTrConv = 0x20;
 constexpr uint8_t kTrReset = 0x40;
 
+constexpr int kProfClasses = 8;
+
 // Everything a kernel needs, passed by value.
 struct Dev {
-    // problem
-    int d, DP, K, family;
-    float nu, nu_plus_d;
-    const float *Pfrag;  // [K][DP/4][64][DP/16] MFMA A-operand fragments of the precision matrices
-    const float *muB;    // [K][4][DP/4]  centre coordinates in B-operand lane order
-    const float *muC;    // [K][4][DP/4]  centre coordinates in accumulator lane order
-    const float *logc2;  // [K] log2 of weight times normaliser
-    const float *lo, *hi;
-    // schedule and hyperparameters
-    int N, m, n_osc, n_conv, n_anti, n_cloud, M, ls_max, grad_mode;
-    float eps_grad, eps_dup, log_delta, momentum, alpha, sigma_cfg, sigma_c, fd_h, ls_c1, curv_eps;
-    uint32_t key0, key1, phase_mask;
-    // population state
+    int P, NT, DS, mmax, Mmax, n_conv_max, n_osc;
+    const ProblemDesc *pd;   // [P]
+    const uint16_t *pid;     // [NT] problem of each sample
+    // population state (rows of stride DS)
     float *X, *F, *G, *V, *Xprev, *Gprev, *Pd, *Gh, *Gp, *ginf;
     uint8_t *stuck, *active, *conv, *removed, *stuck_pre, *status, *reset, *steep, *trace;
-    float *S, *Y, *rho;
+    float *S, *Y, *rho;      // [NT][mmax][DS], [NT][mmax]
     int *head, *cnt;
-    int *lists;  // kNumLists x N
-    Ctl *ctl;
-    CycleRecord *records;  // n_osc entries
-    double *part;          // reduction partials
+    int *lists;              // kNumLists x NT; problem p's list occupies [s0, s0 + N)
+    Ctl *ctl;                // [P]
+    CycleRecord *records;    // [P][n_osc]
+    double *part;            // [P][n_part_blocks][129] reduction partials
     int n_part_blocks;
+    unsigned long long *prof;  // [kProfClasses] evaluations per kernel class
 };
 
-__device__ __forceinline__ int *list_ptr(const Dev &D, int id) { return D.lists + (size_t)id * D.N; }
+__device__ __forceinline__ int *list_ptr(const Dev &D, int id, int s0) { return D.lists + (size_t)id * D.NT + s0; }
 
 }  // namespace chisao

@@ -44,6 +44,37 @@ __device__ __forceinline__ void load_frag(const float *p, float out[MB]) {
     }
 }
 
+constexpr int kMaxClass = 256;  // problems per class (LDS budget: 2 waves per SIMD)
+
+__device__ __forceinline__ int job_count(const EvalArgs &a, int p, const ProblemDesc &pd) {
+    if (a.ext_n >= 0) return a.ext_n;
+    if (a.need_bit && !(pd.phase_mask & (uint32_t)a.need_bit)) return 0;
+    if ((a.step_limit == 1 && a.step >= pd.n_cloud) || (a.step_limit == 2 && a.step >= pd.n_anti)) return 0;
+    return a.list_id >= 0 ? a.D.ctl[p].count[a.list_id] : pd.N;
+}
+__device__ __forceinline__ int centres(const EvalArgs &a, const ProblemDesc &pd) {
+    switch (a.vc_kind) {
+        case kVcTrialRest: return pd.ls_max - 1;
+        case kVcProbes: return pd.M;
+        default: return 1;
+    }
+}
+__device__ __forceinline__ long tiles_of(int count, int V, int &jpw, int &wpj) {
+    if (V <= 0 || count <= 0) {
+        jpw = 1;
+        wpj = 1;
+        return 0;
+    }
+    if (V <= PPW) {
+        jpw = PPW / V;
+        wpj = 1;
+        return (count + jpw - 1) / jpw;
+    }
+    jpw = 1;
+    wpj = (V + PPW - 1) / PPW;
+    return (long)count * wpj;
+}
+
 template <int DP, int FAM, bool GRAD, int CENTER, bool FD>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void eval_kernel(EvalArgs a) {
     constexpr int KS = DP / 4;
@@ -53,76 +84,98 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ev
     __shared__ float s_g[GRAD ? PPW * LD : 1];
     __shared__ float s_f[PPW];
     __shared__ float s_den[PPW];
-    __shared__ int s_s[PPW];    // sample per point, -1 when the lane is idle
+    __shared__ int s_s[PPW];    // sample (or caller row) per point, -1 when the lane is idle
     __shared__ int s_c[PPW];    // centre index within the job
     __shared__ int s_st[PPW];   // stencil index within the centre
     __shared__ int s_pass[PPW];
     __shared__ int s_acc[PPW];
+    __shared__ int s_pref[kMaxClass + 1];
 
     const Dev &D = a.D;
     const int lane = threadIdx.x;
     const int g = lane >> 4, n = lane & 15;
-    const int d = D.d;
-    const int count = a.count_ptr ? *a.count_ptr : a.n_jobs;
-    const int Vs = FD ? 2 * d : 1;
-    const int V = a.Vc * Vs;
-    int jpw, wpj;
-    long n_tiles;
-    if (V <= PPW) {
-        jpw = PPW / V;
-        wpj = 1;
-        n_tiles = (count + jpw - 1) / jpw;
-    } else {
-        jpw = 1;
-        wpj = (V + PPW - 1) / PPW;
-        n_tiles = (long)count * wpj;
+    const bool ext = a.ext_n >= 0;
+    // tile prefix over the problems of the class
+    if (lane == 0) {
+        int acc = 0;
+        s_pref[0] = 0;
+        for (int j = 0; j < a.n_cls; ++j) {
+            const int p = a.cls[j];
+            const ProblemDesc &pd = D.pd[p];
+            const int Vs = FD ? 2 * pd.d : 1;
+            int jpw, wpj;
+            acc += (int)tiles_of(job_count(a, p, pd), centres(a, pd) * Vs, jpw, wpj);
+            s_pref[j + 1] = acc;
+        }
     }
-    const uint32_t kcyc = (uint32_t)D.ctl->k + 1u;
-    const float sigma = (CENTER == kProbe) ? D.ctl->sigma : 0.0f;
+    __syncthreads();
+    const int n_tiles = s_pref[a.n_cls];
 
-    for (long tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+    for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        // ---- the tile's problem ---------------------------------------------
+        int lo_j = 0, hi_j = a.n_cls - 1;
+        while (lo_j < hi_j) {
+            const int mid = (lo_j + hi_j + 1) >> 1;
+            if (s_pref[mid] <= tile) lo_j = mid;
+            else hi_j = mid - 1;
+        }
+        const int p = a.cls[lo_j];
+        const ProblemDesc &pd = D.pd[p];
+        const int ltile = tile - s_pref[lo_j];
+        const int d = pd.d;
+        const int count = job_count(a, p, pd);
+        const int Vc = centres(a, pd);
+        const int r0 = a.vc_kind == kVcTrialRest ? 1 : 0;
+        const int Vs = FD ? 2 * d : 1;
+        const int V = Vc * Vs;
+        int jpw, wpj;
+        (void)tiles_of(count, V, jpw, wpj);
+        const uint32_t kcyc = (uint32_t)D.ctl[p].k + 1u;
+        const float sigma = (CENTER == kProbe) ? D.ctl[p].sigma : 0.0f;
+        const int xs = a.x_stride;
+        const int *lst = (!ext && a.list_id >= 0) ? list_ptr(D, a.list_id, pd.s0) : nullptr;
         // ---- point metadata ------------------------------------------------
         if (lane < PPW) {
-            const int p = lane;
+            const int pt = lane;
             int job, v;
             bool valid;
             if (V <= PPW) {
-                job = (int)(tile * jpw) + p / V;
-                v = p % V;
-                valid = (p < jpw * V) && job < count;
+                job = (int)(ltile * jpw) + pt / V;
+                v = pt % V;
+                valid = (pt < jpw * V) && job < count;
             } else {
-                job = (int)(tile / wpj);
-                v = (int)(tile % wpj) * PPW + p;
+                job = (int)(ltile / wpj);
+                v = (int)(ltile % wpj) * PPW + pt;
                 valid = v < V;
             }
-            s_s[p] = valid ? (a.list ? a.list[job] : job) : -1;
-            s_c[p] = v / Vs;
-            s_st[p] = v % Vs;
-            s_den[p] = 1.0f;
+            s_s[pt] = valid ? (ext ? job : (lst ? lst[job] : pd.s0 + job)) : -1;
+            s_c[pt] = v / Vs;
+            s_st[pt] = v % Vs;
+            s_den[pt] = 1.0f;
         }
         __syncthreads();
         // ---- generate the points (zero padded to DP) -----------------------
         for (int e = lane; e < PPW * KS; e += kWave) {
-            const int p = e / KS, blk = e % KS, c0 = 4 * blk;
-            const int s = s_s[p];
+            const int pt = e / KS, blk = e % KS, c0 = 4 * blk;
+            const int s = s_s[pt];
             float x[4] = {0.f, 0.f, 0.f, 0.f};
             if (s >= 0) {
-                const int ci = s_c[p];
+                const int ci = s_c[pt];
                 float z[4] = {0.f, 0.f, 0.f, 0.f};
                 if constexpr (CENTER == kProbe) {
                     const uint32_t pair = (uint32_t)(ci >> 1);
-                    uint4 o = philox((uint32_t)s, kcyc, (kHLC << 24) | ((uint32_t)a.step << 16) | pair,
-                                     (uint32_t)blk, D.key0, D.key1);
+                    uint4 o = philox((uint32_t)(s - pd.s0), kcyc,
+                                     (kHLC << 24) | ((uint32_t)a.step << 16) | pair, (uint32_t)blk, pd.key0, pd.key1);
                     box_muller4(o, z);
                 }
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int c = c0 + q;
                     if (c < d) {
-                        float xv = a.X[(size_t)s * d + c];
+                        float xv = a.X[(size_t)s * xs + c];
                         if constexpr (CENTER == kTrial) {
-                            const float t = ldexpf(1.0f, -(a.r0 + ci));
-                            xv = fminf(fmaxf(xv + t * D.Pd[(size_t)s * d + c], D.lo[c]), D.hi[c]);
+                            const float t = ldexpf(1.0f, -(r0 + ci));
+                            xv = fminf(fmaxf(xv + t * D.Pd[(size_t)s * D.DS + c], pd.lo[c]), pd.hi[c]);
                         } else if constexpr (CENTER == kProbe) {
                             const float sgn = (ci & 1) ? -1.0f : 1.0f;
                             xv = xv + sigma * sgn * z[q];
@@ -131,19 +184,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ev
                     }
                 }
                 if constexpr (FD) {
-                    const int st = s_st[p];
+                    const int st = s_st[pt];
                     const int cs = st >> 1;
                     if (cs >= c0 && cs < c0 + 4) {
                         const float xc = x[cs - c0];
-                        const float h = D.fd_h > 0.0f ? D.fd_h : ldexpf(fmaxf(1.0f, fabsf(xc)), -8);
+                        const float h = pd.fd_h > 0.0f ? pd.fd_h : ldexpf(fmaxf(1.0f, fabsf(xc)), -8);
                         const float xp = xc + h, xm = xc - h;
                         x[cs - c0] = (st & 1) ? xm : xp;
-                        s_den[p] = xp - xm;
+                        s_den[pt] = xp - xm;
                     }
                 }
             }
 #pragma unroll
-            for (int q = 0; q < 4; ++q) s_pts[p * LD + c0 + q] = x[q];
+            for (int q = 0; q < 4; ++q) s_pts[pt * LD + c0 + q] = x[q];
         }
         __syncthreads();
         // ---- operand registers ---------------------------------------------
@@ -169,10 +222,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ev
                 for (int i = 0; i < KS; ++i) gacc[nb][i] = 0.0f;
         }
         // ---- stream the components -----------------------------------------
-        for (int k = 0; k < D.K; ++k) {
-            const float *pf = D.Pfrag + (size_t)k * KS * kWave * MB + lane * MB;
-            const float *mb_p = D.muB + ((size_t)k * 4 + g) * KS;
-            const float *mc_p = D.muC + ((size_t)k * 4 + g) * KS;
+        const float *Pfrag = pd.Pfrag, *muBk = pd.muB, *muCk = pd.muC, *logc2 = pd.logc2;
+        const float nu = pd.nu, nupd = pd.nu_plus_d;
+        for (int k = 0; k < pd.K; ++k) {
+            const float *pf = Pfrag + (size_t)k * KS * kWave * MB + lane * MB;
+            const float *mb_p = muBk + ((size_t)k * 4 + g) * KS;
+            const float *mc_p = muCk + ((size_t)k * 4 + g) * KS;
             float muB[KS], muC[KS];
 #pragma unroll
             for (int i = 0; i < KS; i += 4) {
@@ -198,7 +253,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ev
                         acc[nb][mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(pa[mb], b, acc[nb][mb], 0, 0, 0);
                 }
             }
-            const float lc2 = D.logc2[k];
+            const float lc2 = logc2[k];
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) {
                 float q = 0.0f;
@@ -212,8 +267,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ev
                 if constexpr (FAM == 0) {
                     l2 = lc2 - q * (0.5f * kLog2e);
                 } else {
-                    l2 = lc2 - (0.5f * D.nu_plus_d * kLog2e) * log1pf(q / D.nu);
-                    w = D.nu_plus_d / (D.nu + q);
+                    l2 = lc2 - (0.5f * nupd * kLog2e) * log1pf(q / nu);
+                    w = nupd / (nu + q);
                 }
                 const float mnew = fmaxf(mrun[nb], l2);
                 const float sc = __builtin_amdgcn_exp2f(mrun[nb] - mnew);
@@ -238,81 +293,83 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ev
         // ---- results to LDS ------------------------------------------------
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
-            const int p = nb * 16 + n;
+            const int pt = nb * 16 + n;
             const float f = (mrun[nb] + __log2f(srun[nb])) * kLn2;
-            if (g == 0) s_f[p] = f;
+            if (g == 0) s_f[pt] = f;
             if constexpr (GRAD) {
                 const float inv = -1.0f / srun[nb];
 #pragma unroll
                 for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) s_g[p * LD + 16 * mb + 4 * g + r] = gacc[nb][mb * 4 + r] * inv;
+                    for (int r = 0; r < 4; ++r) s_g[pt * LD + 16 * mb + 4 * g + r] = gacc[nb][mb * 4 + r] * inv;
             }
         }
         __syncthreads();
-        if (lane == 0) {
+        if (lane == 0 && !ext) {
             int nv = 0;
-            for (int p = 0; p < PPW; ++p) nv += (s_s[p] >= 0);
-            atomicAdd(&D.ctl->evals, nv);
-            atomicAdd(&D.ctl->prof_points[FD ? 3 : CENTER], (unsigned long long)nv);
+            for (int pt = 0; pt < PPW; ++pt) nv += (s_s[pt] >= 0);
+            atomicAdd(&D.ctl[p].evals, nv);
+            atomicAdd(&D.prof[FD ? 3 : CENTER], (unsigned long long)nv);
         }
         // ---- epilogues -----------------------------------------------------
+        const int os = a.out_stride;
         if constexpr (CENTER == kDirect && !FD) {
             if (lane < PPW && s_s[lane] >= 0 && a.F_out) a.F_out[s_s[lane]] = s_f[lane];
             if constexpr (GRAD) {
                 if (a.G_out)
                     for (int e = lane; e < PPW * d; e += kWave) {
-                        const int p = e / d, c = e % d, s = s_s[p];
-                        if (s >= 0) a.G_out[(size_t)s * d + c] = s_g[p * LD + c];
+                        const int pt = e / d, c = e % d, s = s_s[pt];
+                        if (s >= 0) a.G_out[(size_t)s * os + c] = s_g[pt * LD + c];
                     }
             }
         } else if constexpr (FD) {
             if (lane < PPW) {
-                const int p = lane, s = s_s[p], st = s_st[p];
+                const int pt = lane, s = s_s[pt], st = s_st[pt];
                 if (s >= 0 && (st & 1) == 0) {
-                    const float gv = (s_f[p] - s_f[p + 1]) / s_den[p];
+                    const float gv = (s_f[pt] - s_f[pt + 1]) / s_den[pt];
                     const int c = st >> 1;
-                    if constexpr (CENTER == kDirect) a.G_out[(size_t)s * d + c] = gv;
-                    else D.Gp[((size_t)s * D.M + s_c[p]) * d + c] = gv;
+                    if constexpr (CENTER == kDirect) a.G_out[(size_t)s * os + c] = gv;
+                    else D.Gp[((size_t)s * D.Mmax + s_c[pt]) * D.DS + c] = gv;
                 }
             }
         } else if constexpr (CENTER == kProbe) {
             // mean over the job's probes, summed in probe order
-            const float invM = 1.0f / (float)a.Vc;
+            const float invM = 1.0f / (float)Vc;
             for (int e = lane; e < jpw * d; e += kWave) {
-                const int j = e / d, c = e % d, p0 = j * a.Vc, s = s_s[p0];
+                const int j = e / d, c = e % d, p0 = j * Vc, s = s_s[p0];
                 if (s >= 0) {
                     float acc = 0.0f;
-                    for (int mm = 0; mm < a.Vc; ++mm) acc += s_g[(p0 + mm) * LD + c];
-                    D.Gh[(size_t)s * d + c] = acc * invM;
+                    for (int mm = 0; mm < Vc; ++mm) acc += s_g[(p0 + mm) * LD + c];
+                    D.Gh[(size_t)s * D.DS + c] = acc * invM;
                 }
             }
         } else if constexpr (CENTER == kTrial) {
             // Armijo margins f_tr - f - c1 g.(x_tr - x), two lanes per point
+            const int DS = D.DS;
             {
-                const int p = lane >> 1, h = lane & 1, s = s_s[p];
+                const int pt = lane >> 1, h = lane & 1, s = s_s[pt];
                 float dot = 0.0f;
                 if (s >= 0)
                     for (int c = h; c < d; c += 2)
-                        dot += D.G[(size_t)s * d + c] * (s_pts[p * LD + c] - D.X[(size_t)s * d + c]);
+                        dot += D.G[(size_t)s * DS + c] * (s_pts[pt * LD + c] - D.X[(size_t)s * DS + c]);
                 dot += __shfl_xor(dot, 1, kWave);
-                if (h == 0) s_pass[p] = (s >= 0) && (s_f[p] - D.F[s] - D.ls_c1 * dot >= 0.0f);
+                if (h == 0) s_pass[pt] = (s >= 0) && (s_f[pt] - D.F[s] - pd.ls_c1 * dot >= 0.0f);
             }
             __syncthreads();
             if (lane < jpw) {
                 int r = -1;
-                const int p0 = lane * a.Vc;
+                const int p0 = lane * Vc;
                 if (s_s[p0] >= 0)
-                    for (int i = 0; i < a.Vc; ++i)
+                    for (int i = 0; i < Vc; ++i)
                         if (s_pass[p0 + i]) { r = i; break; }
                 s_acc[lane] = r;
             }
             __syncthreads();
             for (int e = lane; e < jpw * d; e += kWave) {
-                const int j = e / d, c = e % d, p0 = j * a.Vc, s = s_s[p0];
+                const int j = e / d, c = e % d, p0 = j * Vc, s = s_s[p0];
                 if (s >= 0 && s_acc[j] >= 0) {
                     const int pa = p0 + s_acc[j];
-                    const size_t o = (size_t)s * d + c;
+                    const size_t o = (size_t)s * DS + c;
                     D.Xprev[o] = D.X[o];
                     D.X[o] = s_pts[pa * LD + c];
                     D.Gprev[o] = D.G[o];
@@ -320,22 +377,22 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ev
                 }
             }
             if (lane < jpw) {
-                const int p0 = lane * a.Vc, s = s_s[p0];
+                const int p0 = lane * Vc, s = s_s[p0];
                 if (s >= 0) {
                     const int r = s_acc[lane];
                     if (r >= 0) {
                         D.F[s] = s_f[p0 + r];
-                        D.status[s] = (uint8_t)(kStAccept | (a.r0 + r));
+                        D.status[s] = (uint8_t)(kStAccept | (r0 + r));
                         if constexpr (!GRAD) {
-                            const int slot = atomicAdd(&D.ctl->count[L_FD], 1);
-                            list_ptr(D, L_FD)[slot] = s;
+                            const int slot = atomicAdd(&D.ctl[p].count[L_FD], 1);
+                            list_ptr(D, L_FD, pd.s0)[slot] = s;
                         }
-                    } else if (a.trial_next >= 0) {
-                        const int slot = atomicAdd(&D.ctl->count[a.trial_next], 1);
-                        list_ptr(D, a.trial_next)[slot] = s;
+                    } else if (a.trial_next >= 0 && pd.ls_max > 1) {
+                        const int slot = atomicAdd(&D.ctl[p].count[a.trial_next], 1);
+                        list_ptr(D, a.trial_next, pd.s0)[slot] = s;
                     } else {
                         D.status[s] = kStFail;
-                        atomicAdd(&D.ctl->ls_fail, 1);
+                        atomicAdd(&D.ctl[p].ls_fail, 1);
                     }
                 }
             }
@@ -366,21 +423,18 @@ static hipError_t dispatch_modes(const EvalArgs &a, int center, bool fd, bool gr
     return hipGetLastError();
 }
 
-hipError_t launch_eval(const EvalArgs &a, int center, bool fd, bool grad, hipStream_t st) {
-    if (a.n_jobs <= 0) return hipSuccess;
-    const int Vs = fd ? 2 * a.D.d : 1;
-    const long V = (long)a.Vc * Vs;
-    long tiles = V <= PPW ? (a.n_jobs + (PPW / V) - 1) / (PPW / V) : (long)a.n_jobs * ((V + PPW - 1) / PPW);
+hipError_t launch_eval(const EvalArgs &a, int DP, int family, int center, bool fd, bool grad, hipStream_t st) {
+    if (a.max_tiles <= 0 || a.n_cls <= 0) return hipSuccess;
+    if (a.n_cls > kMaxClass) return hipErrorInvalidValue;
     const long cap = 8192;
-    dim3 grid((unsigned)(tiles < cap ? tiles : cap));
-    const int fam = a.D.family;
-    switch (a.D.DP) {
-        case 16: return fam ? dispatch_modes<16, 1>(a, center, fd, grad, grid, st)
-                            : dispatch_modes<16, 0>(a, center, fd, grad, grid, st);
-        case 32: return fam ? dispatch_modes<32, 1>(a, center, fd, grad, grid, st)
-                            : dispatch_modes<32, 0>(a, center, fd, grad, grid, st);
-        case 64: return fam ? dispatch_modes<64, 1>(a, center, fd, grad, grid, st)
-                            : dispatch_modes<64, 0>(a, center, fd, grad, grid, st);
+    const dim3 grid((unsigned)(a.max_tiles < cap ? a.max_tiles : cap));
+    switch (DP) {
+        case 16: return family ? dispatch_modes<16, 1>(a, center, fd, grad, grid, st)
+                               : dispatch_modes<16, 0>(a, center, fd, grad, grid, st);
+        case 32: return family ? dispatch_modes<32, 1>(a, center, fd, grad, grid, st)
+                               : dispatch_modes<32, 0>(a, center, fd, grad, grid, st);
+        case 64: return family ? dispatch_modes<64, 1>(a, center, fd, grad, grid, st)
+                               : dispatch_modes<64, 0>(a, center, fd, grad, grid, st);
         default: return hipErrorInvalidValue;
     }
 }

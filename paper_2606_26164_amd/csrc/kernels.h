@@ -9,27 +9,35 @@ namespace chisao {
 
 enum Center { kDirect = 0, kTrial = 1, kProbe = 2 };
 
-// One batched evaluation of the objective at generated points.
-// A job is one sample (list[job], or job itself without a list); it expands
-// into Vc centres (the sample itself, line-search trials, or smoothing
-// probes), and with finite differences each centre into a 2d-point stencil.
+// One batched evaluation of the objective at generated points, over the
+// problems of one class (same padded dimension and family).  A job is one sample; it expands
+// into Vc centres (the sample itself, line-search trials, or smoothing probes)
+// and, with finite differences, each centre into a 2d-point stencil.  Tiles
+// of 32 points never straddle two problems.
+enum VcKind { kVcOne = 0, kVcTrialFirst = 1, kVcTrialRest = 2, kVcProbes = 3 };
+
 struct EvalArgs {
     Dev D;
-    const float *X;         // rows of the samples the centres are built from (stride d)
-    const int *list;        // job -> sample index (nullptr: identity)
-    const int *count_ptr;   // device job count (nullptr: n_jobs)
-    int n_jobs;             // upper bound on the job count (sizes the grid)
-    int Vc;                 // centres per job
-    int r0;                 // backtracking index of the first trial centre
-    int step;               // smoothing step index (probe stream)
-    float *F_out;           // direct centres: value per sample (may be null)
-    float *G_out;           // direct centres: gradient rows per sample (may be null)
-    int trial_next;         // trial centres: list receiving rejected samples (-1: mark failed)
+    const int *cls;       // device: problem ids of this class
+    int n_cls;
+    long max_tiles;       // upper bound on the tile count (sizes the grid)
+    const float *X;       // rows the centres are built from
+    int x_stride;         // DS for the population, d for caller memory
+    int ext_n;            // >= 0: caller memory, jobs 0..ext_n-1 of problem cls[0]; -1: population lists
+    int list_id;          // population jobs: list id, or -1 for every sample of the problem
+    int vc_kind;          // VcKind
+    int step;             // smoothing step index (probe stream)
+    float *F_out;         // direct centres: value per job row (may be null)
+    float *G_out;         // direct centres: gradient rows (may be null)
+    int out_stride;
+    int trial_next;       // trial centres: list receiving rejected samples (-1: mark failed)
+    int need_bit;         // phase_mask bit a problem must have set to take part (0: none)
+    int step_limit;       // 1: only problems with step < n_cloud, 2: step < n_anti, 0: all
 };
 
 // center: kDirect / kTrial / kProbe; fd: stencil around each centre;
 // grad: accumulate the adjoint gradient.
-hipError_t launch_eval(const EvalArgs &a, int center, bool fd, bool grad, hipStream_t st);
+hipError_t launch_eval(const EvalArgs &a, int DP, int family, int center, bool fd, bool grad, hipStream_t st);
 
 // Per-component constants: log2 normalisers (float64 Cholesky of each
 // precision matrix) and the fragment layouts of the precision matrices and
@@ -43,19 +51,21 @@ hipError_t launch_fill_u8(uint8_t *p, uint8_t v, size_t n, hipStream_t st);
 hipError_t launch_uniform_init(const Dev &D, hipStream_t st);
 hipError_t launch_begin_cycle(const Dev &D, hipStream_t st);
 hipError_t launch_reset_counts(const Dev &D, int mask, hipStream_t st);
-hipError_t launch_build_list(const Dev &D, int which, hipStream_t st);
-hipError_t launch_lbfgs_step(const Dev &D, int t, hipStream_t st);
+hipError_t launch_build_unfrozen(const Dev &D, hipStream_t st);
+// L-BFGS step over the samples listed in `samples` (nullptr: all NT), all of
+// whose problems have d <= 16 * cpl.
+hipError_t launch_lbfgs_step(const Dev &D, int t, int cpl, const int *samples, int n_samples, hipStream_t st);
 hipError_t launch_stick(const Dev &D, hipStream_t st);
 hipError_t launch_dedup(const Dev &D, hipStream_t st);
 hipError_t launch_reseed(const Dev &D, hipStream_t st);
 hipError_t launch_sigma(const Dev &D, hipStream_t st);
-hipError_t launch_probe_mean(const Dev &D, hipStream_t st);
+hipError_t launch_probe_mean(const Dev &D, int step, hipStream_t st);
 hipError_t launch_step_size(const Dev &D, const float *Gsrc, int which, hipStream_t st);
-hipError_t launch_hlc_update(const Dev &D, hipStream_t st);
+hipError_t launch_hlc_update(const Dev &D, int step, hipStream_t st);
 hipError_t launch_anti_update(const Dev &D, int step, hipStream_t st);
 hipError_t launch_end_cycle(const Dev &D, int advance, hipStream_t st);
-// Mode export: stuck active samples in ascending index; rows to D.Gh, values to D.Pd,
-// count in ctl->count[O_PEAKS].
-hipError_t launch_mode_list(const Dev &D, hipStream_t st);
+hipError_t launch_mode_list(const Dev &D, int p, int s0, int N, hipStream_t st);
+// Mode export of problem p: its stuck active samples in ascending index, rows
+// to D.Gh and values to D.Pd from row/element s0, count in ctl[p].count[O_PEAKS].
 
 }  // namespace chisao

@@ -1,0 +1,115 @@
+"""Batched handles and graph replay: a batch of problems of uneven d, K, N and
+gradient mode must give, for every problem, bitwise the state that problem
+reaches on a handle of its own (every per-problem reduction has a fixed
+shape, random streams are indexed by the sample's index within its problem),
+and a cycle replayed from a captured hipGraph must give bitwise the state of
+the same kernels enqueued one by one."""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("X", "F", "G", "stuck", "active", "removed", "trace")
+
+
+def _mixed_batch(n_osc=5):
+    specs = [
+        # (seed, d, K, spread, lam, family, N, grad_mode, M, n_conv)
+        (11, 2, 4, 5.0, (0.25, 0.25), W.GAUSS, 700, 1, 10, 10),
+        (12, 16, 24, 10.0, (0.1, 1.0), W.GAUSS, 1500, 0, 4, 12),
+        (13, 64, 16, 20.0, (0.05, 1.0), W.GAUSS, 1100, 1, 16, 18),
+        (14, 8, 12, 8.0, (0.2, 1.0), W.STUDENT_T, 900, 1, 8, 10),
+        (15, 33, 9, 10.0, (0.1, 1.0), W.GAUSS, 333, 1, 5, 16),
+    ]
+    items = []
+    for pid, (seed, d, K, a, lam, fam, N, gm, M, nc) in enumerate(specs):
+        p = W.mixture_problem(seed, d, K, a, lam_range=lam, family=fam, nu=3.0)
+        c = W.RunConfig(N=N, m=6 + pid, n_osc=n_osc, n_conv=nc, M=M, eps_grad=1e-3, grad_mode=gm, seed=7,
+                        problem_id=pid)
+        items.append((p, c, W.uniform_population(seed, N, p.lo, p.hi)))
+    return items
+
+
+def _state(opt, problem=0):
+    s = opt.get_state(history=True, problem=problem)
+    return s
+
+
+def _assert_same(a, b, what):
+    for f in FIELDS + ("S", "Y", "rho", "head", "cnt", "conv", "k", "gr_disabled", "gr_fail"):
+        np.testing.assert_array_equal(np.asarray(a[f]), np.asarray(b[f]), err_msg=f"{what}: field {f}")
+
+
+def test_batched_equals_single_bitwise():
+    from paper_2606_26164_amd.api import Optimizer
+
+    items = _mixed_batch()
+    n_osc = items[0][1].n_osc
+    with Optimizer.batched(items) as opt:
+        stats_b = opt.cycle(n_osc - 1, stats=True)
+        states_mid = [_state(opt, p) for p in range(len(items))]
+        stats_b += opt.cycle(1, stats=True)
+        states_b = [_state(opt, p) for p in range(len(items))]
+        modes_b = [opt.modes(p) for p in range(len(items))]
+    for p, (prob, cfg, x0) in enumerate(items):
+        print(f"problem {p}: d={prob.d} K={prob.K} N={cfg.N} grad_mode={cfg.grad_mode}", flush=True)
+        with Optimizer(prob, cfg, x0) as one:
+            stats_1 = one.cycle(n_osc - 1, stats=True)
+            _assert_same(states_mid[p], _state(one), f"problem {p} after {n_osc - 1} cycles")
+            stats_1 += one.cycle(1, stats=True)
+            _assert_same(states_b[p], _state(one), f"problem {p} at the end")
+            m1 = one.modes()
+        assert [s[p] for s in stats_b] == stats_1
+        np.testing.assert_array_equal(modes_b[p].X, m1.X)
+        np.testing.assert_array_equal(modes_b[p].F, m1.F)
+
+
+@pytest.mark.parametrize("grad_mode", [1, 0])
+def test_graph_replay_equals_eager_bitwise(grad_mode):
+    from paper_2606_26164_amd import _lib as L
+    from paper_2606_26164_amd.api import Optimizer
+
+    prob = W.mixture_problem(21, 16, 20, 10.0, lam_range=(0.1, 1.0))
+    cfg = W.RunConfig(N=3000, m=8, n_osc=6, n_conv=12, M=6, eps_grad=1e-3, grad_mode=grad_mode, seed=5)
+    x0 = W.uniform_population(21, cfg.N, prob.lo, prob.hi)
+    out = []
+    for flags in (0, L.FLAG_NO_GRAPH):
+        with Optimizer(prob, cfg.with_(flags=flags), x0) as opt:
+            stats = opt.cycle(cfg.n_osc, stats=True)
+            out.append((stats, _state(opt), opt.modes()))
+    assert out[0][0] == out[1][0]
+    _assert_same(out[0][1], out[1][1], "graph vs eager")
+    np.testing.assert_array_equal(out[0][2].X, out[1][2].X)
+
+
+def test_graph_replay_deterministic_across_handles():
+    from paper_2606_26164_amd.api import Optimizer
+
+    items = _mixed_batch(n_osc=3)
+    res = []
+    for _ in range(2):
+        with Optimizer.batched(items) as opt:
+            opt.cycle(3)
+            res.append([_state(opt, p) for p in range(len(items))])
+    for p in range(len(items)):
+        _assert_same(res[0][p], res[1][p], f"problem {p}, second handle")
+
+
+def test_batch_validation():
+    from paper_2606_26164_amd import _lib as L
+    from paper_2606_26164_amd.api import Optimizer
+
+    items = _mixed_batch()
+    p, c, x0 = items[1]
+    bad = list(items)
+    bad[1] = (p, c.with_(n_osc=c.n_osc + 1), x0)
+    with pytest.raises(L.ChisaoError) as ei:
+        Optimizer.batched(bad)
+    assert ei.value.code == L.E_INVAL and "n_osc" in str(ei.value)
+    with Optimizer.batched(items) as opt:
+        with pytest.raises(L.ChisaoError):
+            opt.get_state(problem=len(items))
+        with pytest.raises(L.ChisaoError):
+            opt.modes(problem=-1)

@@ -553,3 +553,35 @@ def test_config1_modes_match_brute_force_grid():
         assert np.abs(gm - x).max(1).min() < 1e-3
     for x in gm:
         assert np.abs(X - x).max(1).min() < 1e-3
+
+
+def test_newton_reference_modes_match_grid_at_d2():
+    """The Newton reference used to score recall agrees with the brute-force
+    grid on config 1, and with the oracle's own full run."""
+    from oracle.modes import newton_modes
+
+    prob, cfg, x0 = W.config1()
+    Xn, Fn = newton_modes(prob)
+    gm, gf = _grid_modes(prob)
+    gm = gm[gf >= gf.max() + np.log(0.1)]
+    assert len(Xn) == len(gm)
+    for x in Xn:
+        assert np.abs(gm - x).max(1).min() < 1e-6
+
+
+def test_newton_reference_student_t_hessian():
+    """Student-t Hessian of the reference against central differences of the
+    analytic gradient."""
+    from oracle.modes import value_grad_hess
+
+    prob = W.mixture_problem(19, 5, 3, 2.0, lam_range=(0.3, 1.0), family=W.STUDENT_T, nu=3.0)
+    x = np.random.default_rng(3).normal(size=5)
+    f, g, H = value_grad_hess(prob, x)
+    op = O.OracleProblem(prob)
+    f2, g2 = op.eval(x[None])
+    assert np.isclose(f, f2[0], rtol=1e-12)
+    np.testing.assert_allclose(g, g2[0], rtol=1e-10, atol=1e-12)
+    h = 1e-5
+    Hfd = np.array([(op.eval((x + h * e)[None])[1][0] - op.eval((x - h * e)[None])[1][0]) / (2 * h)
+                    for e in np.eye(5)])
+    np.testing.assert_allclose(H, Hfd.T, rtol=1e-5, atol=1e-6)

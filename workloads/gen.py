@@ -62,6 +62,7 @@ class RunConfig:
     phase_mask: int = 0x7E
     seed: int = 0
     problem_id: int = 0
+    flags: int = 0  # bit 0: run cycles without graph replay
 
     def with_(self, **kw) -> "RunConfig":
         return replace(self, **kw)
