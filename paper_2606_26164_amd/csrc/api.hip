@@ -18,7 +18,7 @@
 #include <tuple>
 #include <vector>
 
-#include "../../include/chisao.h"
+#include "chisao.h"
 #include "kernels.h"
 
 using namespace chisao;
@@ -70,11 +70,11 @@ struct EvalClass {
     const int *pids_dev;  // into the handle's class table
     std::vector<int> pids;
 };
-// A group of samples served by one L-BFGS launch.
+// The problems of one lane layout of the L-BFGS kernel: their samples are a
+// contiguous global range [g0, g0 + n).
 struct LbfgsClass {
     int cpl;
-    const int *samples_dev;  // nullptr: every sample of the handle
-    int n;
+    int g0, n;
 };
 
 struct chisao_ctx {
@@ -247,8 +247,24 @@ extern "C" int chisao_init_batched(chisao_handle *out, int n_problems, const chi
         ALLOC(bad, int, 1);
         HIP_GO(hipMemsetAsync(bad, 0, sizeof(int), st));
         // ---- per-problem constants ----
+        // Samples are laid out problem after problem, ordered by (padded d,
+        // family, gradient mode), so the problems of each launch class own a
+        // contiguous range of samples.
+        std::vector<int> order(P);
+        for (int p = 0; p < n_problems; ++p) order[p] = p;
+        auto key = [&](int p) {
+            return std::make_tuple(pad_dim(ps[p].d), ps[p].family, cs[p].grad_mode);
+        };
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key(a) < key(b); });
+        std::vector<int> s0_of(P);
+        {
+            int acc = 0;
+            for (int p : order) {
+                s0_of[p] = acc;
+                acc += cs[p].N;
+            }
+        }
         h->pdh.resize(P);
-        int s0 = 0;
         for (int p = 0; p < n_problems; ++p) {
             const chisao_problem &pr = ps[p];
             const chisao_config &c = cs[p];
@@ -285,8 +301,7 @@ extern "C" int chisao_init_batched(chisao_handle *out, int n_problems, const chi
             q.lo = lo;
             q.hi = hi;
             q.N = c.N;
-            q.s0 = s0;
-            s0 += c.N;
+            q.s0 = s0_of[p];
             q.m = c.m;
             q.n_conv = n_conv[p];
             q.n_anti = c.n_anti;
@@ -329,24 +344,10 @@ extern "C" int chisao_init_batched(chisao_handle *out, int n_problems, const chi
         std::vector<int> table;
         for (int p = 0; p < n_problems; ++p) table.push_back(p);  // pid_seq
         for (auto &kv : ecl) table.insert(table.end(), kv.second.begin(), kv.second.end());
-        std::vector<std::vector<int>> lsamples;
-        for (auto &kv : lcl) {
-            std::vector<int> v;
-            if (lcl.size() > 1)
-                for (int p : kv.second)
-                    for (int i = 0; i < h->pdh[p].N; ++i) v.push_back(h->pdh[p].s0 + i);
-            lsamples.push_back(v);
-        }
-        size_t tot = table.size();
-        for (auto &v : lsamples) tot += v.size();
         int *tab_dev;
-        ALLOC(tab_dev, int, tot);
-        {
-            std::vector<int> all(table);
-            for (auto &v : lsamples) all.insert(all.end(), v.begin(), v.end());
-            HIP_GO(hipMemcpyAsync(tab_dev, all.data(), sizeof(int) * all.size(), hipMemcpyHostToDevice, st));
-            HIP_GO(hipStreamSynchronize(st));  // the host vectors go out of scope
-        }
+        ALLOC(tab_dev, int, table.size());
+        HIP_GO(hipMemcpyAsync(tab_dev, table.data(), sizeof(int) * table.size(), hipMemcpyHostToDevice, st));
+        HIP_GO(hipStreamSynchronize(st));  // the host vector goes out of scope
         h->pid_seq = tab_dev;
         size_t off = P;
         for (auto &kv : ecl) {
@@ -357,19 +358,16 @@ extern "C" int chisao_init_batched(chisao_handle *out, int n_problems, const chi
             off += kv.second.size();
             h->eclasses.push_back(c);
         }
-        size_t li = 0;
         for (auto &kv : lcl) {
             LbfgsClass c;
             c.cpl = kv.first;
-            if (lcl.size() > 1) {
-                c.samples_dev = tab_dev + off;
-                c.n = (int)lsamples[li].size();
-                off += lsamples[li].size();
-            } else {
-                c.samples_dev = nullptr;
-                c.n = (int)N;
+            c.g0 = (int)N;
+            int end = 0;
+            for (int p : kv.second) {
+                c.g0 = std::min(c.g0, h->pdh[p].s0);
+                end = std::max(end, h->pdh[p].s0 + h->pdh[p].N);
             }
-            ++li;
+            c.n = end - c.g0;
             h->lclasses.push_back(c);
         }
         // ---- population state ----
@@ -399,6 +397,7 @@ extern "C" int chisao_init_batched(chisao_handle *out, int n_problems, const chi
         ALLOC(D.head, int, N);
         ALLOC(D.cnt, int, N);
         ALLOC(D.lists, int, N * kNumLists);
+        ALLOC(D.flag, uint8_t, N);
         ALLOC(D.ctl, Ctl, P);
         ALLOC(D.records, CycleRecord, P * (size_t)D.n_osc);
         ALLOC(D.part, double, P * (size_t)D.n_part_blocks * 129);
@@ -541,34 +540,42 @@ static hipError_t phase_converge(chisao_ctx *h) {
     if ((e = launch_begin_cycle(D, st)) != hipSuccess) return e;
     if ((e = eval_list(h, L_ACT, D.F, D.G, true, 0, 0, 0)) != hipSuccess) return e;
     for (int t = 1; t <= D.n_conv_max + 1; ++t) {
-        if ((e = launch_reset_counts(D, (1 << L_T1) | (1 << L_T2) | (1 << L_FD), st)) != hipSuccess) return e;
+        // the steppers of iteration t go to list_out; t+1 reads them back
+        const int list_in = t == 1 ? L_ACT : ((t - 1) % 2 ? L_T1 : L_T1B);
+        const int list_out = t % 2 ? L_T1 : L_T1B;
+        if ((e = launch_reset_counts(D, (1 << list_out) | (1 << L_T2) | (1 << L_FD), st)) != hipSuccess) return e;
         for (const LbfgsClass &lc : h->lclasses)
             if ((e = timed(h, CHISAO_PROF_LBFGS,
-                           [&] { return launch_lbfgs_step(D, t, lc.cpl, lc.samples_dev, lc.n, st); })) != hipSuccess)
+                           [&] { return launch_lbfgs_step(D, t, lc.cpl, list_in, lc.g0, lc.n, st); })) != hipSuccess)
                 return e;
         if (t > D.n_conv_max) break;
+        if ((e = launch_compact(D, list_in, list_out, -1, false, D.prof + CHISAO_PROF_LBFGS, st)) != hipSuccess)
+            return e;
+        // first trial t = 1 for every stepper; the rest (speculative, all at
+        // once) for those whose first trial failed
         for (const EvalClass &c : h->eclasses) {
-            const bool adj = c.grad_mode == CHISAO_GRAD_ADJOINT;
             EvalArgs a = base_args(h, c);
-            a.list_id = L_T1;
+            a.list_id = list_out;
             a.vc_kind = kVcTrialFirst;
             a.trial_next = L_T2;
-            if ((e = run_eval(h, c, a, kTrial, false, adj)) != hipSuccess) return e;
+            if ((e = run_eval(h, c, a, kTrial, false, c.grad_mode == CHISAO_GRAD_ADJOINT)) != hipSuccess) return e;
         }
+        if ((e = launch_compact(D, list_out, L_T2, L_FD, true, nullptr, st)) != hipSuccess) return e;
         for (const EvalClass &c : h->eclasses) {
-            const bool adj = c.grad_mode == CHISAO_GRAD_ADJOINT;
             EvalArgs a = base_args(h, c);
             a.list_id = L_T2;
             a.vc_kind = kVcTrialRest;
             a.trial_next = -1;
-            if ((e = run_eval(h, c, a, kTrial, false, adj)) != hipSuccess) return e;
-            if (!adj) {
-                EvalArgs b = base_args(h, c);
-                b.list_id = L_FD;
-                b.vc_kind = kVcOne;
-                b.G_out = D.G;
-                if ((e = run_eval(h, c, b, kDirect, true, false)) != hipSuccess) return e;
-            }
+            if ((e = run_eval(h, c, a, kTrial, false, c.grad_mode == CHISAO_GRAD_ADJOINT)) != hipSuccess) return e;
+        }
+        if ((e = launch_compact(D, L_T2, -1, L_FD, true, nullptr, st)) != hipSuccess) return e;
+        for (const EvalClass &c : h->eclasses) {
+            if (c.grad_mode == CHISAO_GRAD_ADJOINT) continue;
+            EvalArgs b = base_args(h, c);
+            b.list_id = L_FD;
+            b.vc_kind = kVcOne;
+            b.G_out = D.G;
+            if ((e = run_eval(h, c, b, kDirect, true, false)) != hipSuccess) return e;
         }
     }
     return hipSuccess;

@@ -134,7 +134,9 @@ struct ProblemDesc {
 // Per-problem control block: counters and scalars that decide the
 // data-dependent control flow of a cycle without a host round trip.
 // ---------------------------------------------------------------------------
-enum ListId { L_ACT = 0, L_T1, L_T2, L_FD, L_UNF, L_STK, O_SLOTS, O_FREE, O_PEAKS, kNumLists };
+// L_T1 and L_T1B alternate between L-BFGS iterations: one holds the samples
+// that took a step in the previous iteration, the other collects this one's.
+enum ListId { L_ACT = 0, L_T1, L_T1B, L_T2, L_FD, L_UNF, L_STK, O_SLOTS, O_FREE, O_PEAKS, kNumLists };
 
 struct Ctl {
     int k;  // cycles completed
@@ -181,6 +183,7 @@ struct Dev {
     float *S, *Y, *rho;      // [NT][mmax][DS], [NT][mmax]
     int *head, *cnt;
     int *lists;              // kNumLists x NT; problem p's list occupies [s0, s0 + N)
+    uint8_t *flag;           // [NT] per list position: a producer's verdict, read by the compaction
     Ctl *ctl;                // [P]
     CycleRecord *records;    // [P][n_osc]
     double *part;            // [P][n_part_blocks][129] reduction partials
@@ -189,5 +192,35 @@ struct Dev {
 };
 
 __device__ __forceinline__ int *list_ptr(const Dev &D, int id, int s0) { return D.lists + (size_t)id * D.NT + s0; }
+
+// Lanes with `want` each take one unit of a per-problem counter (counter(p)
+// gives its address): one atomic per distinct problem among the wave's lanes
+// instead of one per lane.  Returns the counter's previous value plus the
+// lane's rank among the lanes of its problem, or -1 without `want`.  Every
+// lane of the wave must make the call.
+template <class F>
+__device__ __forceinline__ int wave_claim(bool want, int p, F counter) {
+    const int lane = __lane_id();
+    unsigned long long pending = __ballot(want);
+    int slot = -1;
+    while (pending) {
+        const int leader = __ffsll((unsigned long long)pending) - 1;
+        const int pl = __shfl(p, leader, kWave);
+        const bool mine = want && p == pl;
+        const unsigned long long grp = __ballot(mine);
+        int base = 0;
+        if (lane == leader) base = atomicAdd(counter(pl), (int)__popcll(grp));
+        base = __shfl(base, leader, kWave);
+        if (mine) slot = base + (int)__popcll(grp & ((1ull << lane) - 1ull));
+        pending &= ~grp;
+    }
+    return slot;
+}
+
+// Wave-aggregated append of sample s to list `id` of problem p.
+__device__ __forceinline__ void wave_append(const Dev &D, int id, bool want, int p, int s) {
+    const int slot = wave_claim(want, p, [&](int q) { return &D.ctl[q].count[id]; });
+    if (want) list_ptr(D, id, D.pd[p].s0)[slot] = s;
+}
 
 }  // namespace chisao

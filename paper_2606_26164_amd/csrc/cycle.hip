@@ -37,11 +37,6 @@ hipError_t launch_fill_u8(uint8_t *p, uint8_t v, size_t n, hipStream_t st) {
     return hipGetLastError();
 }
 
-__device__ __forceinline__ void append(const Dev &D, int id, int p, int s) {
-    const int slot = atomicAdd(&D.ctl[p].count[id], 1);
-    list_ptr(D, id, D.pd[p].s0)[slot] = s;
-}
-
 // Uniform starting population in the box from the INIT stream (counter =
 // sample index within its problem).
 __global__ void uniform_init_kernel(Dev D) {
@@ -84,21 +79,25 @@ __global__ void begin_ctl_kernel(Dev D) {
 }
 
 __global__ void begin_samples_kernel(Dev D) {
-    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < D.NT; s += gridDim.x * blockDim.x) {
-        D.stuck[s] = 0;
-        D.removed[s] = 0;
-        D.stuck_pre[s] = 0;
-        D.conv[s] = 0;
-        D.status[s] = 0;
-        D.reset[s] = 0;
-        D.steep[s] = 0;
-        D.cnt[s] = 0;
-        const int p = D.pid[s];
-        D.head[s] = D.pd[p].m - 1;
-        if (D.active[s]) {
-            append(D, L_ACT, p, s);
-            atomicAdd(&D.ctl[p].n_active, 1);
+    // the loop bound is uniform per wave: the list appends are wave-wide
+    for (int b = blockIdx.x * blockDim.x; b < D.NT; b += gridDim.x * blockDim.x) {
+        const int s = b + threadIdx.x;
+        const bool in = s < D.NT;
+        const int p = in ? D.pid[s] : 0;
+        const bool act = in && D.active[s];
+        if (in) {
+            D.stuck[s] = 0;
+            D.removed[s] = 0;
+            D.stuck_pre[s] = 0;
+            D.conv[s] = 0;
+            D.status[s] = 0;
+            D.reset[s] = 0;
+            D.steep[s] = 0;
+            D.cnt[s] = 0;
+            D.head[s] = D.pd[p].m - 1;
         }
+        wave_append(D, L_ACT, act, p, s);
+        wave_claim(act, p, [&](int q) { return &D.ctl[q].n_active; });
     }
 }
 
@@ -122,10 +121,86 @@ hipError_t launch_reset_counts(const Dev &D, int mask, hipStream_t st) {
     return hipGetLastError();
 }
 
+// List compaction.  A block takes 256 consecutive list positions; per problem
+// present among them (positions are grouped by problem, so usually one) it
+// scans the flags with wave ballots and claims room in the destination list
+// with one global atomic, instead of one atomic per producing wave: atomics on
+// one address serialise in the L2, which made per-wave appends the dominant
+// cost of the L-BFGS step.
+__global__ __launch_bounds__(kBlock) void compact_kernel(Dev D, int src, int dst1, int dst2, int count_fail,
+                                                         unsigned long long *tally) {
+    __shared__ int s_pmin;
+    __shared__ int s_wc[3][kWavesPerBlock];
+    __shared__ int s_base[3];
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    for (int b = blockIdx.x * kBlock; b < D.NT; b += gridDim.x * kBlock) {
+        const int j = b + tid;
+        int p = 0, v = 0, s = -1;
+        if (j < D.NT) {
+            p = D.pid[j];
+            if (j - D.pd[p].s0 < D.ctl[p].count[src]) {
+                v = D.flag[j];
+                if (v) s = D.lists[(size_t)src * D.NT + j];
+            }
+        }
+        bool pending = v != 0;
+        for (;;) {
+            if (tid == 0) s_pmin = 0x7FFFFFFF;
+            __syncthreads();
+            if (pending) atomicMin(&s_pmin, p);
+            __syncthreads();
+            const int pl = s_pmin;
+            if (pl == 0x7FFFFFFF) break;
+            const bool mine = pending && p == pl;
+            unsigned long long bal[3];
+#pragma unroll
+            for (int o = 0; o < 3; ++o) {
+                bal[o] = __ballot(mine && v == o + 1);
+                if (lane == 0) s_wc[o][w] = (int)__popcll(bal[o]);
+            }
+            __syncthreads();
+            if (tid < 3) {
+                int tot = 0;
+                for (int k = 0; k < kWavesPerBlock; ++k) tot += s_wc[tid][k];
+                int base = 0;
+                if (tot > 0) {
+                    const int dst = tid == 0 ? dst1 : (tid == 1 ? dst2 : -1);
+                    if (dst >= 0) base = atomicAdd(&D.ctl[pl].count[dst], tot);
+                    else if (tid == 2 && count_fail) atomicAdd(&D.ctl[pl].ls_fail, tot);
+                    if (tid == 0 && tally) atomicAdd(tally, (unsigned long long)tot);
+                }
+                s_base[tid] = base;
+            }
+            __syncthreads();
+            if (mine && v <= 2) {
+                const int dst = v == 1 ? dst1 : dst2;
+                if (dst >= 0) {
+                    int off = s_base[v - 1] + (int)__popcll(bal[v - 1] & below);
+                    for (int k = 0; k < w; ++k) off += s_wc[v - 1][k];
+                    list_ptr(D, dst, D.pd[pl].s0)[off] = s;
+                }
+            }
+            pending = pending && !mine;
+            __syncthreads();
+        }
+    }
+}
+
+hipError_t launch_compact(const Dev &D, int src, int dst1, int dst2, bool count_fail, unsigned long long *tally,
+                          hipStream_t st) {
+    hipLaunchKernelGGL(compact_kernel, dim3(grid_for(D.NT, kBlock, 4096)), dim3(kBlock), 0, st, D, src, dst1, dst2,
+                       (int)count_fail, tally);
+    return hipGetLastError();
+}
+
 // Unfrozen list (active and not stuck) for Phases 5-6.
 __global__ void build_unfrozen_kernel(Dev D) {
-    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < D.NT; s += gridDim.x * blockDim.x)
-        if (D.active[s] && !D.stuck[s]) append(D, L_UNF, D.pid[s], s);
+    for (int b = blockIdx.x * blockDim.x; b < D.NT; b += gridDim.x * blockDim.x) {
+        const int s = b + threadIdx.x;
+        const bool in = s < D.NT;
+        wave_append(D, L_UNF, in && D.active[s] && !D.stuck[s], in ? D.pid[s] : 0, s);
+    }
 }
 
 hipError_t launch_build_unfrozen(const Dev &D, hipStream_t st) {
@@ -167,18 +242,23 @@ __device__ __forceinline__ float row_dot(const float a[CPL], const float b[CPL])
 }
 
 template <int MM, int CPL>
-__global__ __launch_bounds__(kBlock) void lbfgs_step_kernel(Dev D, int t, const int *samples, int n_samples) {
+__global__ __launch_bounds__(kBlock) void lbfgs_step_kernel(Dev D, int t, int list_in, int g0, int n) {
     const int lane = threadIdx.x & (kWave - 1);
     const int wv = threadIdx.x / kWave;
     const int rr = lane >> 4, l16 = lane & 15;
     const int c0 = l16 * CPL;
     const int DS = D.DS, mx = D.mmax;
-    const int groups = (n_samples + 3) / 4;
+    const int groups = (n + 3) / 4;
     for (int grp = blockIdx.x * kWavesPerBlock + wv; grp < groups; grp += gridDim.x * kWavesPerBlock) {
-        const int idx = grp * 4 + rr;
-        const int s = idx < n_samples ? (samples ? samples[idx] : idx) : -1;
+        // slot j of the list segment of problem pid[j] (segments start at s0)
+        const int pos = g0 + grp * 4 + rr;
+        int s = -1, p = 0;
+        if (pos < g0 + n) {
+            p = D.pid[pos];
+            if (pos - D.pd[p].s0 < D.ctl[p].count[list_in]) s = D.lists[(size_t)list_in * D.NT + pos];
+        }
+        if (__ballot(s >= 0) == 0) continue;
         const bool act = s >= 0 && D.active[s];
-        const int p = s >= 0 ? D.pid[s] : 0;
         const ProblemDesc &pd = D.pd[p];
         const int d = pd.d, m = pd.m;
         const size_t row = (size_t)(act ? s : 0) * DS;
@@ -201,7 +281,6 @@ __global__ __launch_bounds__(kBlock) void lbfgs_step_kernel(Dev D, int t, const 
             }
         } else {
             const uint8_t stt = act ? D.status[s] : 0;
-            const bool stalled = act && cflag == 2;
             const bool accepted = (stt & kStAccept) != 0;
             float sv[CPL], yv[CPL];
             {
@@ -219,11 +298,7 @@ __global__ __launch_bounds__(kBlock) void lbfgs_step_kernel(Dev D, int t, const 
             const float ss = row_dot<CPL>(sv, sv);
             const float yy = row_dot<CPL>(yv, yv);
             const float gi = row16_max(gabs);
-            if (stalled) {
-                // the failed search started from an empty history: every later
-                // iteration repeats it exactly and fails the same way
-                if (l16 == 0 && t - 1 <= pd.n_conv) D.trace[(size_t)(t - 1) * D.NT + s] = kTrFail;
-            } else if (stt != 0) {
+            if (stt != 0) {
                 uint8_t code = D.reset[s] ? kTrReset : 0;
                 if (accepted) {
                     code |= (uint8_t)(stt & 0x0F);
@@ -249,6 +324,10 @@ __global__ __launch_bounds__(kBlock) void lbfgs_step_kernel(Dev D, int t, const 
                     D.ginf[s] = gi;
                     D.conv[s] = converged ? 1 : (stall ? 2 : 0);
                     D.trace[(size_t)(t - 1) * D.NT + s] = code;
+                    // the failed search started from an empty history: every
+                    // later iteration would repeat it exactly and fail alike
+                    if (stall)
+                        for (int r = t; r <= pd.n_conv; ++r) D.trace[(size_t)r * D.NT + s] = kTrFail;
                     D.status[s] = 0;
                     D.reset[s] = 0;
                     D.cnt[s] = cnt;
@@ -258,7 +337,10 @@ __global__ __launch_bounds__(kBlock) void lbfgs_step_kernel(Dev D, int t, const 
         }
         // ---- two-loop recursion (all four rows take part in the reductions) --
         const bool go = !done && t <= pd.n_conv;
-        if (__ballot(go) == 0) continue;
+        if (__ballot(go) == 0) {
+            if (s >= 0 && l16 == 0) D.flag[pos] = 0;
+            continue;
+        }
         const int cnt_go = go ? cnt : 0;
         const int cmax = (int)wave_max((float)cnt_go);
         float hs[MM][CPL], hy[MM][CPL], rh[MM], al[MM];
@@ -309,33 +391,32 @@ __global__ __launch_bounds__(kBlock) void lbfgs_step_kernel(Dev D, int t, const 
         }
         row_store<CPL>(D.Pd + row, d, c0, go, pv);
         if (go && l16 == 0) {
-            atomicAdd(&D.prof[4], 1ull);
             D.steep[s] = (cnt == 0) || rst;
             if (rst) {
                 D.cnt[s] = 0;
                 D.head[s] = m - 1;
                 D.reset[s] = 1;
             }
-            append(D, L_T1, p, s);
         }
+        if (s >= 0 && l16 == 0) D.flag[pos] = go ? 1 : 0;
     }
 }
 
 template <int CPL>
-static void launch_lbfgs_cpl(const Dev &D, int t, const int *samples, int n, hipStream_t st) {
+static void launch_lbfgs_cpl(const Dev &D, int t, int li, int g0, int n, hipStream_t st) {
     const dim3 grid(grid_for((n + 3) / 4, kWavesPerBlock, 8192)), block(kBlock);
-    if (D.mmax <= 4) hipLaunchKernelGGL((lbfgs_step_kernel<4, CPL>), grid, block, 0, st, D, t, samples, n);
-    else if (D.mmax <= 8) hipLaunchKernelGGL((lbfgs_step_kernel<8, CPL>), grid, block, 0, st, D, t, samples, n);
-    else if (D.mmax <= 12) hipLaunchKernelGGL((lbfgs_step_kernel<12, CPL>), grid, block, 0, st, D, t, samples, n);
-    else if (D.mmax <= 16) hipLaunchKernelGGL((lbfgs_step_kernel<16, CPL>), grid, block, 0, st, D, t, samples, n);
-    else hipLaunchKernelGGL((lbfgs_step_kernel<32, CPL>), grid, block, 0, st, D, t, samples, n);
+    if (D.mmax <= 4) hipLaunchKernelGGL((lbfgs_step_kernel<4, CPL>), grid, block, 0, st, D, t, li, g0, n);
+    else if (D.mmax <= 8) hipLaunchKernelGGL((lbfgs_step_kernel<8, CPL>), grid, block, 0, st, D, t, li, g0, n);
+    else if (D.mmax <= 12) hipLaunchKernelGGL((lbfgs_step_kernel<12, CPL>), grid, block, 0, st, D, t, li, g0, n);
+    else if (D.mmax <= 16) hipLaunchKernelGGL((lbfgs_step_kernel<16, CPL>), grid, block, 0, st, D, t, li, g0, n);
+    else hipLaunchKernelGGL((lbfgs_step_kernel<32, CPL>), grid, block, 0, st, D, t, li, g0, n);
 }
 
-hipError_t launch_lbfgs_step(const Dev &D, int t, int cpl, const int *samples, int n_samples, hipStream_t st) {
-    if (n_samples <= 0) return hipSuccess;
-    if (cpl <= 1) launch_lbfgs_cpl<1>(D, t, samples, n_samples, st);
-    else if (cpl <= 2) launch_lbfgs_cpl<2>(D, t, samples, n_samples, st);
-    else launch_lbfgs_cpl<4>(D, t, samples, n_samples, st);
+hipError_t launch_lbfgs_step(const Dev &D, int t, int cpl, int list_in, int g0, int n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    if (cpl <= 1) launch_lbfgs_cpl<1>(D, t, list_in, g0, n, st);
+    else if (cpl <= 2) launch_lbfgs_cpl<2>(D, t, list_in, g0, n, st);
+    else launch_lbfgs_cpl<4>(D, t, list_in, g0, n, st);
     return hipGetLastError();
 }
 
@@ -374,15 +455,13 @@ __global__ void stick_kernel(Dev D) {
     const float fmax = ordered_to_float(D.ctl[p].fmax_ord);
     const float gate = fmax + pd.log_delta;
     if (blockIdx.x == 0 && threadIdx.x == 0) D.ctl[p].f_max = fmax;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < pd.N; i += gridDim.x * blockDim.x) {
-        const int s = pd.s0 + i;
-        if (!D.active[s]) continue;
-        const bool st = (D.ginf[s] < pd.eps_grad) && (D.F[s] >= gate);
-        D.stuck_pre[s] = st;
-        if (st) {
-            append(D, L_STK, p, s);
-            atomicAdd(&D.ctl[p].n_stuck, 1);
-        }
+    for (int b = blockIdx.x * blockDim.x; b < pd.N; b += gridDim.x * blockDim.x) {
+        const int i = b + threadIdx.x, s = pd.s0 + i;
+        const bool act = i < pd.N && D.active[s];
+        const bool st = act && (D.ginf[s] < pd.eps_grad) && (D.F[s] >= gate);
+        if (act) D.stuck_pre[s] = st;
+        wave_append(D, L_STK, st, p, s);
+        wave_claim(st, p, [&](int q) { return &D.ctl[q].n_stuck; });
     }
 }
 
@@ -461,12 +540,15 @@ __global__ void clear_removed_kernel(Dev D) {
 }
 
 __global__ void dedup_finalize_kernel(Dev D) {
-    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < D.NT; s += gridDim.x * blockDim.x) {
-        const bool st = D.stuck_pre[s] && !D.removed[s];
-        D.stuck[s] = st;
-        const int p = D.pid[s];
-        if (D.removed[s]) atomicAdd(&D.ctl[p].K_lost, 1);
-        if (st) atomicAdd(&D.ctl[p].n_modes, 1);
+    for (int b = blockIdx.x * blockDim.x; b < D.NT; b += gridDim.x * blockDim.x) {
+        const int s = b + threadIdx.x;
+        const bool in = s < D.NT;
+        const bool rm = in && D.removed[s];
+        const bool st = in && D.stuck_pre[s] && !rm;
+        if (in) D.stuck[s] = st;
+        const int p = in ? D.pid[s] : 0;
+        wave_claim(rm, p, [&](int q) { return &D.ctl[q].K_lost; });
+        wave_claim(st, p, [&](int q) { return &D.ctl[q].n_modes; });
     }
 }
 

@@ -98,15 +98,24 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ev
     // tile prefix over the problems of the class
     if (lane == 0) {
         int acc = 0;
+        unsigned long long pts = 0;
         s_pref[0] = 0;
         for (int j = 0; j < a.n_cls; ++j) {
             const int p = a.cls[j];
             const ProblemDesc &pd = D.pd[p];
             const int Vs = FD ? 2 * pd.d : 1;
+            const int jobs = job_count(a, p, pd);
             int jpw, wpj;
-            acc += (int)tiles_of(job_count(a, p, pd), centres(a, pd) * Vs, jpw, wpj);
+            acc += (int)tiles_of(jobs, centres(a, pd) * Vs, jpw, wpj);
             s_pref[j + 1] = acc;
+            // evaluation counts, once per launch (block 0) rather than per tile
+            if (blockIdx.x == 0 && !ext && jobs > 0) {
+                const int nv = jobs * centres(a, pd) * Vs;
+                atomicAdd(&D.ctl[p].evals, nv);
+                pts += (unsigned long long)nv;
+            }
         }
+        if (blockIdx.x == 0 && pts) atomicAdd(&D.prof[FD ? 3 : CENTER], pts);
     }
     __syncthreads();
     const int n_tiles = s_pref[a.n_cls];
@@ -305,12 +314,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ev
             }
         }
         __syncthreads();
-        if (lane == 0 && !ext) {
-            int nv = 0;
-            for (int pt = 0; pt < PPW; ++pt) nv += (s_s[pt] >= 0);
-            atomicAdd(&D.ctl[p].evals, nv);
-            atomicAdd(&D.prof[FD ? 3 : CENTER], (unsigned long long)nv);
-        }
         // ---- epilogues -----------------------------------------------------
         const int os = a.out_stride;
         if constexpr (CENTER == kDirect && !FD) {
@@ -376,24 +379,25 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ev
                     if constexpr (GRAD) D.G[o] = s_g[pa * LD + c];
                 }
             }
+            // verdict per list position for the compaction that follows:
+            // 1 try the remaining trials, 2 accepted (the finite-difference
+            // gradient is still due), 3 the search failed, 0 nothing to do
             if (lane < jpw) {
-                const int p0 = lane * Vc, s = s_s[p0];
-                if (s >= 0) {
+                const int p0 = lane * Vc, sl = s_s[p0];
+                if (sl >= 0) {
                     const int r = s_acc[lane];
+                    uint8_t verdict;
                     if (r >= 0) {
-                        D.F[s] = s_f[p0 + r];
-                        D.status[s] = (uint8_t)(kStAccept | (r0 + r));
-                        if constexpr (!GRAD) {
-                            const int slot = atomicAdd(&D.ctl[p].count[L_FD], 1);
-                            list_ptr(D, L_FD, pd.s0)[slot] = s;
-                        }
+                        D.F[sl] = s_f[p0 + r];
+                        D.status[sl] = (uint8_t)(kStAccept | (r0 + r));
+                        verdict = GRAD ? 0 : 2;
                     } else if (a.trial_next >= 0 && pd.ls_max > 1) {
-                        const int slot = atomicAdd(&D.ctl[p].count[a.trial_next], 1);
-                        list_ptr(D, a.trial_next, pd.s0)[slot] = s;
+                        verdict = 1;
                     } else {
-                        D.status[s] = kStFail;
-                        atomicAdd(&D.ctl[p].ls_fail, 1);
+                        D.status[sl] = kStFail;
+                        verdict = 3;
                     }
+                    D.flag[pd.s0 + (int)(ltile * jpw) + lane] = verdict;
                 }
             }
         }

@@ -33,7 +33,16 @@ def _mixed_batch(n_osc=5):
 
 
 def _state(opt, problem=0):
+    """State with the L-BFGS ring buffers cut to their live pairs (slots past
+    a sample's pair count hold whatever the allocation held)."""
     s = opt.get_state(history=True, problem=problem)
+    N, m = s["rho"].shape
+    live = np.zeros((N, m), bool)
+    for i in range(N):
+        for j in range(s["cnt"][i]):
+            live[i, (s["head"][i] - j) % m] = True
+    for f in ("S", "Y", "rho"):
+        s[f] = np.where(live.reshape(live.shape + (1,) * (s[f].ndim - 2)), s[f], 0)
     return s
 
 
@@ -108,8 +117,16 @@ def test_batch_validation():
     with pytest.raises(L.ChisaoError) as ei:
         Optimizer.batched(bad)
     assert ei.value.code == L.E_INVAL and "n_osc" in str(ei.value)
+    import ctypes as C
+
     with Optimizer.batched(items) as opt:
-        with pytest.raises(L.ChisaoError):
-            opt.get_state(problem=len(items))
-        with pytest.raises(L.ChisaoError):
-            opt.modes(problem=-1)
+        st = L.State()
+        n = C.c_int(0)
+        for bad_p in (len(items), -1):
+            assert opt.lib.chisao_get_state(opt.h, bad_p, C.byref(st)) == L.E_INVAL
+            assert opt.lib.chisao_set_state(opt.h, bad_p, C.byref(st)) == L.E_INVAL
+            assert opt.lib.chisao_modes(opt.h, bad_p, None, None, 0, C.byref(n)) == L.E_INVAL
+            assert opt.lib.chisao_eval(opt.h, bad_p, None, 0, None, None, 1) == L.E_INVAL
+        # a batch keeps one cycle count: setting another k on one problem is refused
+        st.k = 1
+        assert opt.lib.chisao_set_state(opt.h, 0, C.byref(st)) == L.E_INVAL
