@@ -96,6 +96,15 @@ __device__ __forceinline__ float row16_max(float v) {
     return v;
 }
 
+// Sum over the four 16-lane rows (lanes l, l^16, l^32, l^48) with the gfx950
+// row-swap permutes (no LDS traffic); every lane receives the same bits.
+__device__ __forceinline__ float rows4_sum(float v) {
+    const auto a = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    v = __uint_as_float(a[0]) + __uint_as_float(a[1]);
+    const auto b = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    return __uint_as_float(b[0]) + __uint_as_float(b[1]);
+}
+
 // Total order on floats as signed ints, for exact atomic max.
 __device__ __forceinline__ int float_to_ordered(float f) {
     int i = __float_as_int(f);

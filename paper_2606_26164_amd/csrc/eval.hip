@@ -31,18 +31,34 @@ constexpr int PPW = 32;  // points per wave
 constexpr float kLog2e = 1.4426950408889634f;
 constexpr float kLn2 = 0.6931471805599453f;
 
+// Pointers into the global address space (plain loads through them compile
+// to global_load, which only the vector-memory counter tracks).
+typedef const float __attribute__((address_space(1))) gfloat;
+typedef const f32x4 __attribute__((address_space(1))) gf32x4;
+typedef const f32x2 __attribute__((address_space(1))) gf32x2;
+__device__ __forceinline__ const gfloat *as_global(const float *p) { return (const gfloat *)p; }
+
 template <int MB>
-__device__ __forceinline__ void load_frag(const float *p, float out[MB]) {
+__device__ __forceinline__ void load_frag(const gfloat *p, float out[MB]) {
     if constexpr (MB == 4) {
-        f32x4 v = *reinterpret_cast<const f32x4 *>(p);
+        const f32x4 v = *reinterpret_cast<const gf32x4 *>(p);
         out[0] = v[0]; out[1] = v[1]; out[2] = v[2]; out[3] = v[3];
     } else if constexpr (MB == 2) {
-        f32x2 v = *reinterpret_cast<const f32x2 *>(p);
+        const f32x2 v = *reinterpret_cast<const gf32x2 *>(p);
         out[0] = v[0]; out[1] = v[1];
     } else {
         out[0] = *p;
     }
 }
+
+// One component's operands in registers: precision-matrix fragments,
+// centre coordinates in B- and accumulator-lane order, log2 weight.
+template <int KS, int MB>
+struct CompRegs {
+    float pa[KS][MB];
+    float muB[KS], muC[KS];
+    float lc2;
+};
 
 constexpr int kMaxClass = 256;  // problems per class (LDS budget: 2 waves per SIMD)
 
@@ -76,7 +92,7 @@ __device__ __forceinline__ long tiles_of(int count, int V, int &jpw, int &wpj) {
 }
 
 template <int DP, int FAM, bool GRAD, int CENTER, bool FD>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void eval_kernel(EvalArgs a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void eval_kernel(EvalArgs a) {
     constexpr int KS = DP / 4;
     constexpr int MB = DP / 16;
     constexpr int LD = DP + 1;  // padded row: conflict-free column reads
@@ -231,20 +247,31 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ev
                 for (int i = 0; i < KS; ++i) gacc[nb][i] = 0.0f;
         }
         // ---- stream the components -----------------------------------------
-        const float *Pfrag = pd.Pfrag, *muBk = pd.muB, *muCk = pd.muC, *logc2 = pd.logc2;
+        // Component k+1's operands are loaded into a second register set while
+        // component k is contracted (the loop is unrolled by two so the sets
+        // alternate without copies).  The loads go through global-address-space
+        // pointers: flat loads would also count against the LDS counter, and
+        // the cross-lane shuffles of the epilogue would then wait for them.
+        const gfloat *Pfrag = as_global(pd.Pfrag), *muBk = as_global(pd.muB), *muCk = as_global(pd.muC),
+                     *logc2 = as_global(pd.logc2);
         const float nu = pd.nu, nupd = pd.nu_plus_d;
-        for (int k = 0; k < pd.K; ++k) {
-            const float *pf = Pfrag + (size_t)k * KS * kWave * MB + lane * MB;
-            const float *mb_p = muBk + ((size_t)k * 4 + g) * KS;
-            const float *mc_p = muCk + ((size_t)k * 4 + g) * KS;
-            float muB[KS], muC[KS];
+        CompRegs<KS, MB> ra, rb;
+        auto load = [&](int k, CompRegs<KS, MB> &r) {
+            const gfloat *pf = Pfrag + (size_t)k * KS * kWave * MB + lane * MB;
+            const gfloat *mb_p = muBk + ((size_t)k * 4 + g) * KS;
+            const gfloat *mc_p = muCk + ((size_t)k * 4 + g) * KS;
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) load_frag<MB>(pf + (size_t)ks * kWave * MB, r.pa[ks]);
 #pragma unroll
             for (int i = 0; i < KS; i += 4) {
-                f32x4 vb = *reinterpret_cast<const f32x4 *>(mb_p + i);
-                f32x4 vc = *reinterpret_cast<const f32x4 *>(mc_p + i);
-                muB[i] = vb[0]; muB[i + 1] = vb[1]; muB[i + 2] = vb[2]; muB[i + 3] = vb[3];
-                muC[i] = vc[0]; muC[i + 1] = vc[1]; muC[i + 2] = vc[2]; muC[i + 3] = vc[3];
+                const f32x4 vb = *reinterpret_cast<const gf32x4 *>(mb_p + i);
+                const f32x4 vc = *reinterpret_cast<const gf32x4 *>(mc_p + i);
+                r.muB[i] = vb[0]; r.muB[i + 1] = vb[1]; r.muB[i + 2] = vb[2]; r.muB[i + 3] = vb[3];
+                r.muC[i] = vc[0]; r.muC[i + 1] = vc[1]; r.muC[i + 2] = vc[2]; r.muC[i + 3] = vc[3];
             }
+            r.lc2 = logc2[k];
+        };
+        auto step = [&](const CompRegs<KS, MB> &r) {
             f32x4 acc[NB][MB];
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb)
@@ -252,31 +279,28 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ev
                 for (int mb = 0; mb < MB; ++mb) acc[nb][mb] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks) {
-                float pa[MB];
-                load_frag<MB>(pf + (size_t)ks * kWave * MB, pa);
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb) {
-                    const float b = xB[nb][ks] - muB[ks];
+                    const float b = xB[nb][ks] - r.muB[ks];
 #pragma unroll
                     for (int mb = 0; mb < MB; ++mb)
-                        acc[nb][mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(pa[mb], b, acc[nb][mb], 0, 0, 0);
+                        acc[nb][mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(r.pa[ks][mb], b, acc[nb][mb], 0, 0, 0);
                 }
             }
-            const float lc2 = logc2[k];
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) {
                 float q = 0.0f;
 #pragma unroll
                 for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) q = fmaf(xC[nb][mb * 4 + r] - muC[mb * 4 + r], acc[nb][mb][r], q);
-                q += __shfl_xor(q, 16, kWave);
-                q += __shfl_xor(q, 32, kWave);
+                    for (int rr = 0; rr < 4; ++rr)
+                        q = fmaf(xC[nb][mb * 4 + rr] - r.muC[mb * 4 + rr], acc[nb][mb][rr], q);
+                q = rows4_sum(q);
                 float l2, w = 1.0f;
                 if constexpr (FAM == 0) {
-                    l2 = lc2 - q * (0.5f * kLog2e);
+                    l2 = r.lc2 - q * (0.5f * kLog2e);
                 } else {
-                    l2 = lc2 - (0.5f * nupd * kLog2e) * log1pf(q / nu);
+                    l2 = r.lc2 - (0.5f * nupd * kLog2e) * log1pf(q / nu);
                     w = nupd / (nu + q);
                 }
                 const float mnew = fmaxf(mrun[nb], l2);
@@ -294,10 +318,21 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ev
 #pragma unroll
                     for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-                        for (int r = 0; r < 4; ++r)
-                            gacc[nb][mb * 4 + r] = fmaf(pw, acc[nb][mb][r], gacc[nb][mb * 4 + r]);
+                        for (int rr = 0; rr < 4; ++rr)
+                            gacc[nb][mb * 4 + rr] = fmaf(pw, acc[nb][mb][rr], gacc[nb][mb * 4 + rr]);
                 }
             }
+        };
+        const int K = pd.K;
+        // (the prefetch past the last component reloads it: no branch, so the
+        // wait before each step covers only the set it uses)
+        load(0, ra);
+        for (int k = 0; k < K; k += 2) {
+            load(min(k + 1, K - 1), rb);
+            step(ra);
+            if (k + 1 >= K) break;
+            load(min(k + 2, K - 1), ra);
+            step(rb);
         }
         // ---- results to LDS ------------------------------------------------
 #pragma unroll
