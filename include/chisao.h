@@ -59,7 +59,9 @@ typedef struct {
     const float *prec;   /* [K*d*d] exactly symmetric positive-definite precision (inverse covariance / inverse scale) */
     const float *lo;     /* [d] lower box bounds */
     const float *hi;     /* [d] upper box bounds, hi > lo */
-    float noise_sigma;   /* additive evaluation noise; must be 0 in this version */
+    float noise_sigma;   /* >= 0: every value the method evaluates is f(x) + noise_sigma * z, z ~ N(0,1)
+                            drawn per evaluation (Sec. 5.7); gradients of the adjoint mode stay exact.
+                            chisao_eval returns the noise-free f. */
 } chisao_problem;
 
 /* Schedule and hyperparameters (Sec. 3.6, Table 1).  A value <= 0 in a field
@@ -84,7 +86,8 @@ typedef struct {
     float ls_c1;        /* Armijo constant of the backtracking line search */
     int32_t ls_max;     /* backtracking trials t = 1, 1/2, ..., 2^-(ls_max-1); 1..16 */
     float curv_eps;     /* a pair is stored when s'y > curv_eps |s| |y| */
-    int32_t gate_reps;  /* reserved (noisy objectives); must be 0 */
+    int32_t gate_reps;  /* noisy problems: the quality gate compares the mean of this many fresh noisy
+                           evaluations per sample (0: M); 0..4096 */
     uint32_t phase_mask;/* bit p enables phase p for p = 3..6 (ablation hook); 0x7E = all */
     uint64_t seed;      /* key of every random stream */
     uint32_t problem_id;/* mixed into the key, so problems draw independent streams */
@@ -96,7 +99,7 @@ typedef struct {
 /* Per-cycle statistics (host struct). */
 typedef struct {
     int32_t k;          /* 1-based index of the cycle these figures belong to */
-    float f_max;        /* largest value over active samples after Phase 1 */
+    float f_max;        /* largest value over active samples after Phase 1 (gate values when noisy) */
     int32_t n_stuck;    /* samples passing the stick test (before deduplication) */
     int32_t K_lost;     /* duplicates removed by Phase 3 */
     int32_t n_modes;    /* stuck samples surviving deduplication */
@@ -134,7 +137,8 @@ typedef struct {
     int32_t *head;      /* [N] */
     int32_t *cnt;       /* [N] */
     uint8_t *conv;      /* [N] last Phase 1: 1 converged, 2 stalled (a search from an empty history failed,
-                           so every later iteration would repeat it), 0 otherwise */
+                           so every later iteration would repeat it; never with noise), 0 otherwise */
+    float *Fg;          /* [N] quality-gate values of a noisy problem after Phase 1 (get only) */
 } chisao_state;
 
 /* Kernel timing of the work enqueued by chisao_cycle / chisao_run_phases

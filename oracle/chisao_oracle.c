@@ -77,6 +77,7 @@ typedef struct {
     int32_t gr_disabled, gr_fail, gr_used_last, gr_prev_modes;
     double f_max, sigma, alpha_c, alpha_a;
     int32_t K_lost, n_stuck, n_modes, reseed_kind, n_free, n_unfrozen;
+    double *Fg; /* quality-gate values (noisy objectives only) */
 } orc_state;
 
 typedef struct {
@@ -248,10 +249,43 @@ static double eval_point(const orc_problem *P, const double *logc, const double 
 
 static size_t eval_work_len(const orc_problem *P) { return (size_t)P->K * (1 + P->d); }
 
+/* ------------------------------------------------------------------------ */
+/* Likelihood noise (Sec. 5.7): every evaluation the method makes returns    */
+/* f(x) + sigma_n z with a fresh standard normal z.  Reading: z is the first */
+/* normal of the NOISE stream at counter (sample, cycle, step << 16 | sub);  */
+/* sub names the evaluation within the step: the centre value 0, line-search */
+/* trial r, and 0x1000 / 0x2000 | probe << 7 / 0x3000 plus the stencil index */
+/* (2j for x + h e_j, 2j + 1 for x - h e_j) for the central differences of   */
+/* Phase 1, of smoothing probes and of anti-convergence.  The noise does not */
+/* depend on x, so the analytic gradient is noise-free.                       */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    const orc_config *C;
+    double sigma;
+    uint32_t sample, cycle, step, sub;
+} noise_t;
+
+enum { NZ_FD1 = 0x1000, NZ_FD_PROBE = 0x2000, NZ_FD_ANTI = 0x3000 };
+
+static double noise_at(const noise_t *nz, uint32_t sub)
+{
+    if (!nz || !(nz->sigma > 0.0)) return 0.0;
+    double z[4];
+    normals4(nz->C, nz->sample, nz->cycle, ((uint32_t)PH_NOISE << 24) | (nz->step << 16) | sub, 0u, z);
+    return nz->sigma * z[0];
+}
+
+static noise_t noise_for(const orc_problem *P, const orc_config *C, const orc_state *S, int i, int step,
+                         uint32_t sub)
+{
+    noise_t nz = { C, P->noise_sigma, (uint32_t)i, (uint32_t)S->k + 1u, (uint32_t)step, sub };
+    return nz;
+}
+
 /* Central finite-difference gradient: g_j = (f(x+h_j e_j) - f(x-h_j e_j)) /
  * ((x_j+h_j) - (x_j-h_j)); the stencil points are not clamped. */
 static void fd_grad_point(const orc_problem *P, const double *logc, double fd_h, const double *x, double *g,
-                          double *work, double *xs)
+                          double *work, double *xs, const noise_t *nz)
 {
     int d = P->d;
     for (int j = 0; j < d; ++j) xs[j] = x[j];
@@ -259,9 +293,9 @@ static void fd_grad_point(const orc_problem *P, const double *logc, double fd_h,
         double h = fd_h > 0.0 ? fd_h : ldexp(fmax(1.0, fabs(x[j])), -8);
         double xp = x[j] + h, xm = x[j] - h;
         xs[j] = xp;
-        double fp = eval_point(P, logc, xs, NULL, work);
+        double fp = eval_point(P, logc, xs, NULL, work) + (nz ? noise_at(nz, nz->sub + 2u * j) : 0.0);
         xs[j] = xm;
-        double fm = eval_point(P, logc, xs, NULL, work);
+        double fm = eval_point(P, logc, xs, NULL, work) + (nz ? noise_at(nz, nz->sub + 2u * j + 1u) : 0.0);
         xs[j] = x[j];
         g[j] = (fp - fm) / (xp - xm);
     }
@@ -290,7 +324,8 @@ void orc_fd_grad_batch(const orc_problem *P, const double *logc, double fd_h, in
         double *work = (double *)malloc(sizeof(double) * eval_work_len(P));
         double *xs = (double *)malloc(sizeof(double) * d);
 #pragma omp for schedule(dynamic, 4)
-        for (int i = 0; i < n; ++i) fd_grad_point(P, logc, fd_h, X + (size_t)i * d, G + (size_t)i * d, work, xs);
+        for (int i = 0; i < n; ++i)
+            fd_grad_point(P, logc, fd_h, X + (size_t)i * d, G + (size_t)i * d, work, xs, NULL);
         free(xs);
         free(work);
     }
@@ -340,12 +375,13 @@ static void scratch_free(scratch_t *s)
     free(s->work); free(s->xs); free(s->p); free(s->r); free(s->xtr); free(s->gtr); free(s->alpha); free(s->margins);
 }
 
-/* The gradient the method uses at x: analytic, or central differences. */
+/* The gradient the method uses at x: analytic (noise-free), or central
+ * differences of noisy values with the stencil noise named by nz. */
 static void method_grad(const orc_problem *P, const double *logc, const orc_config *C, const double *x, double *g,
-                        scratch_t *s)
+                        scratch_t *s, const noise_t *nz)
 {
     if (C->grad_mode == 1) (void)eval_point(P, logc, x, g, s->work);
-    else fd_grad_point(P, logc, C->fd_h, x, g, s->work, s->xs);
+    else fd_grad_point(P, logc, C->fd_h, x, g, s->work, s->xs, nz);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -430,7 +466,8 @@ static void fold_replay(orc_replay *R, const sample_replay_t *sr, int N)
 
 /* ------------------------------------------------------------------------ */
 /* Phase 1: release all, then n_conv batched L-BFGS ascent iterations.       */
-/* Readings: projected Armijo backtracking t = 2^-i (c1, ls_max trials),     */
+/* Readings: projected Armijo backtracking t = 2^-i (c1, ls_max trials;     */
+/* relaxed by 2 sigma_n for noisy objectives),                               */
 /* failure means no move and a cleared history; the scaling gamma is         */
 /* s'y/y'y of the newest pair (1/max(|g|,1) with none); a pair is stored     */
 /* when s'y > curv_eps |s||y|; a sample whose gradient sup-norm falls below  */
@@ -445,6 +482,12 @@ static void lbfgs_iteration(const orc_problem *P, const double *logc, const orc_
     double f = S->F[i];
     uint8_t code = 0;
     const uint8_t *forced = (R && R->trace_in) ? &R->trace_in[(size_t)iter * C->N + i] : NULL;
+    const noise_t nz = noise_for(P, C, S, i, iter, 0u);
+    /* With evaluation noise the sufficient-increase test is relaxed by twice
+     * the noise level (the noise-aware Armijo condition of Berahas, Byrd and
+     * Nocedal, SIAM J. Optim. 29 (2019)): the plain test on two noisy values
+     * rejects most steps once the true gain falls below the noise. */
+    const double relax = 2.0 * P->noise_sigma;
 
     orc_two_loop(d, m, S->cnt[i], S->head[i], Sh, Yh, rh, g, sc->p, sc->alpha);
     double gp = dot(d, g, sc->p);
@@ -463,9 +506,9 @@ static void lbfgs_iteration(const orc_problem *P, const double *logc, const orc_
         double step = ldexp(1.0, -t);
         for (int j = 0; j < d; ++j) sc->xtr[j] = x[j] + step * sc->p[j];
         clamp_box(P, sc->xtr);
-        double ftr = eval_point(P, logc, sc->xtr, NULL, sc->work);
+        double ftr = eval_point(P, logc, sc->xtr, NULL, sc->work) + noise_at(&nz, (uint32_t)t);
         for (int j = 0; j < d; ++j) sc->r[j] = sc->xtr[j] - x[j];
-        sc->margins[t] = ftr - f - C->ls_c1 * dot(d, g, sc->r);
+        sc->margins[t] = ftr - f - C->ls_c1 * dot(d, g, sc->r) + relax;
         n_eval = t + 1;
         if (sc->margins[t] >= 0.0) { own = t; break; }
     }
@@ -484,9 +527,9 @@ static void lbfgs_iteration(const orc_problem *P, const double *logc, const orc_
                 double step = ldexp(1.0, -t);
                 for (int j = 0; j < d; ++j) sc->xtr[j] = x[j] + step * sc->p[j];
                 clamp_box(P, sc->xtr);
-                double ftr = eval_point(P, logc, sc->xtr, NULL, sc->work);
+                double ftr = eval_point(P, logc, sc->xtr, NULL, sc->work) + noise_at(&nz, (uint32_t)t);
                 for (int j = 0; j < d; ++j) sc->r[j] = sc->xtr[j] - x[j];
-                sc->margins[t] = ftr - f - C->ls_c1 * dot(d, g, sc->r);
+                sc->margins[t] = ftr - f - C->ls_c1 * dot(d, g, sc->r) + relax;
             }
             double tol = R->tol_f * fmax(1.0, fabs(f));
             double mgn;
@@ -506,8 +549,12 @@ static void lbfgs_iteration(const orc_problem *P, const double *logc, const orc_
         double step = ldexp(1.0, -use);
         for (int j = 0; j < d; ++j) sc->xtr[j] = x[j] + step * sc->p[j];
         clamp_box(P, sc->xtr);
-        double fnew = eval_point(P, logc, sc->xtr, C->grad_mode == 1 ? sc->gtr : NULL, sc->work);
-        if (C->grad_mode != 1) fd_grad_point(P, logc, C->fd_h, sc->xtr, sc->gtr, sc->work, sc->xs);
+        /* the accepted trial's value, as the search saw it (same noise draw) */
+        double fnew = eval_point(P, logc, sc->xtr, C->grad_mode == 1 ? sc->gtr : NULL, sc->work) +
+                      noise_at(&nz, (uint32_t)use);
+        noise_t nzf = nz;
+        nzf.sub = NZ_FD1;
+        if (C->grad_mode != 1) fd_grad_point(P, logc, C->fd_h, sc->xtr, sc->gtr, sc->work, sc->xs, &nzf);
         /* curvature pair for F = -f: s = x_new - x, y = grad F(x_new) - grad F(x) */
         double *s = sc->r, *y = sc->p;
         for (int j = 0; j < d; ++j) { s[j] = sc->xtr[j] - x[j]; y[j] = -(sc->gtr[j] - g[j]); }
@@ -580,8 +627,9 @@ int orc_phase_converge(const orc_problem *P, const double *logc, const orc_confi
             uint8_t code = TR_NONE;
             if (S->active[i] && !err) {
                 double *x = S->X + (size_t)i * d, *g = S->G + (size_t)i * d;
-                S->F[i] = eval_point(P, logc, x, C->grad_mode == 1 ? g : NULL, sc.work);
-                if (C->grad_mode != 1) fd_grad_point(P, logc, C->fd_h, x, g, sc.work, sc.xs);
+                const noise_t nz0 = noise_for(P, C, S, i, 0, 0u), nzf = noise_for(P, C, S, i, 0, NZ_FD1);
+                S->F[i] = eval_point(P, logc, x, C->grad_mode == 1 ? g : NULL, sc.work) + noise_at(&nz0, 0u);
+                if (C->grad_mode != 1) fd_grad_point(P, logc, C->fd_h, x, g, sc.work, sc.xs, &nzf);
                 double gi = nrminf(d, g);
                 int conv = gi < C->eps_grad;
                 if (R && R->trace_in && R->trace_in[i] != TR_NONE) {
@@ -653,12 +701,58 @@ int orc_lbfgs_iterate(const orc_problem *P, const double *logc, const orc_config
 /* Phase 2: stick test.  f_max is the largest value over active samples;     */
 /* stuck = (|grad f|_inf < eps_grad) and (f >= f_max + log delta).           */
 /* ------------------------------------------------------------------------ */
-int orc_phase_stick(const orc_problem *P, const orc_config *C, orc_state *S, orc_replay *R)
+/* The value the quality gate, the deduplication order and the mode output
+ * use: f as the search saw it, or with noise the gate value. */
+static const double *gate_values(const orc_problem *P, const orc_state *S)
+{
+    return (P->noise_sigma > 0.0 && S->Fg) ? S->Fg : S->F;
+}
+
+/* Gate value under noise (reading of Sec. 5.7, whose method the paper leaves
+ * to SunBURST): the mean of R fresh noisy evaluations at x_i, R = gate_reps
+ * (M when not given), i.e. f(x_i) + sigma_n (1/R) sum_r z_r with z_r the
+ * normals of the GATE stream at counter (sample, cycle, GATE << 24, block). */
+static int compute_gate_values(const orc_problem *P, const double *logc, const orc_config *C, orc_state *S)
 {
     int N = C->N, d = P->d;
+    int R = C->gate_reps > 0 ? C->gate_reps : C->M;
+    int err = 0;
+#pragma omp parallel
+    {
+        double *work = (double *)malloc(sizeof(double) * eval_work_len(P));
+        if (!work) {
+#pragma omp atomic write
+            err = 1;
+        }
+#pragma omp for schedule(dynamic, 4)
+        for (int i = 0; i < N; ++i) {
+            if (!S->active[i] || !work) continue;
+            double f = eval_point(P, logc, S->X + (size_t)i * d, NULL, work);
+            double zs = 0.0;
+            for (int b = 0; 4 * b < R; ++b) {
+                double z[4];
+                normals4(C, (uint32_t)i, (uint32_t)S->k + 1u, (uint32_t)PH_GATE << 24, (uint32_t)b, z);
+                for (int q = 0; q < 4 && 4 * b + q < R; ++q) zs += z[q];
+            }
+            S->Fg[i] = f + P->noise_sigma * (zs / R);
+        }
+        free(work);
+    }
+    return err ? ORC_ENOMEM : ORC_OK;
+}
+
+int orc_phase_stick(const orc_problem *P, const double *logc, const orc_config *C, orc_state *S, orc_replay *R)
+{
+    int N = C->N, d = P->d;
+    if (P->noise_sigma > 0.0) {
+        if (!S->Fg) return ORC_EINVAL;
+        int rc = compute_gate_values(P, logc, C, S);
+        if (rc) return rc;
+    }
+    const double *Fv = gate_values(P, S);
     double fmax_ = -INFINITY;
     for (int i = 0; i < N; ++i)
-        if (S->active[i] && S->F[i] > fmax_) fmax_ = S->F[i];
+        if (S->active[i] && Fv[i] > fmax_) fmax_ = Fv[i];
     S->f_max = fmax_;
     double gate = fmax_ + C->log_delta;
     sample_replay_t *sr = (sample_replay_t *)calloc((size_t)N, sizeof(sample_replay_t));
@@ -669,14 +763,14 @@ int orc_phase_stick(const orc_problem *P, const orc_config *C, orc_state *S, orc
         double gi = 0.0;
         if (S->active[i]) {
             gi = nrminf(d, S->G + (size_t)i * d);
-            st = (gi < C->eps_grad) && (S->F[i] >= gate);
+            st = (gi < C->eps_grad) && (Fv[i] >= gate);
         }
         if (R && R->stuck_in && S->active[i]) {
             int gpu = R->stuck_in[i] ? 1 : 0;
             sr[i].n_dec++;
             if (gpu != st) {
                 double mg = (gi - C->eps_grad) / C->eps_grad;
-                double mf = (S->F[i] - gate) / fmax(1.0, fabs(S->F[i]));
+                double mf = (Fv[i] - gate) / fmax(1.0, fabs(Fv[i]));
                 int border = (fabs(mg) <= R->tol_g) || (fabs(mf) <= R->tol_f);
                 note_disagreement(&sr[i], border, fabs(mg) < fabs(mf) ? mg : mf, 0, KIND_STICK);
                 st = gpu;
@@ -702,6 +796,7 @@ int orc_phase_dedup(const orc_problem *P, const orc_config *C, orc_state *S, orc
 {
     int N = C->N, d = P->d;
     int dedup_on = (C->phase_mask >> 3) & 1;
+    const double *Fv = gate_values(P, S);
     uint8_t *rem = (uint8_t *)calloc((size_t)N, 1);
     sample_replay_t *sr = (sample_replay_t *)calloc((size_t)N, sizeof(sample_replay_t));
     if (!rem || !sr) { free(rem); free(sr); return ORC_ENOMEM; }
@@ -717,11 +812,11 @@ int orc_phase_dedup(const orc_problem *P, const orc_config *C, orc_state *S, orc
                 double dist = 0.0;
                 for (int l = 0; l < d; ++l) dist = fmax(dist, fabs(xi[l] - xj[l]));
                 int near = dist < C->eps_dup;
-                int above = (S->F[i] > S->F[j]) || (S->F[i] == S->F[j] && i < j);
+                int above = (Fv[i] > Fv[j]) || (Fv[i] == Fv[j] && i < j);
                 if (near && above) removed = 1;
                 if (R && (fabs(dist - C->eps_dup) <= R->tol_dist ||
                           (dist < C->eps_dup + R->tol_dist &&
-                           fabs(S->F[i] - S->F[j]) <= R->tol_f * fmax(1.0, fabs(S->F[j])))))
+                           fabs(Fv[i] - Fv[j]) <= R->tol_f * fmax(1.0, fabs(Fv[j])))))
                     border = 1;
             }
             if (R && R->removed_in) {
@@ -993,7 +1088,8 @@ int orc_phase_hlc(const orc_problem *P, const double *logc, const orc_config *C,
                     normal_vec(C, (uint32_t)i, k, ((uint32_t)PH_HLC << 24) | ((uint32_t)step << 16) | (uint32_t)pair,
                                d, z);
                     for (int l = 0; l < d; ++l) sc.xtr[l] = x[l] + sigma * sgn * z[l];
-                    method_grad(P, logc, C, sc.xtr, sc.gtr, &sc);
+                    const noise_t nzp = noise_for(P, C, S, i, step, NZ_FD_PROBE | ((uint32_t)mm << 7));
+                    method_grad(P, logc, C, sc.xtr, sc.gtr, &sc, &nzp);
                     for (int l = 0; l < d; ++l) gh[l] += sc.gtr[l];
                 }
                 for (int l = 0; l < d; ++l) gh[l] /= M;
@@ -1053,7 +1149,8 @@ int orc_phase_anti(const orc_problem *P, const double *logc, const orc_config *C
 #pragma omp for schedule(dynamic, 2)
             for (int i = 0; i < N; ++i) {
                 if (!(S->active[i] && !S->stuck[i])) continue;
-                method_grad(P, logc, C, S->X + (size_t)i * d, Gt + (size_t)i * d, &sc);
+                const noise_t nza = noise_for(P, C, S, i, step, NZ_FD_ANTI);
+                method_grad(P, logc, C, S->X + (size_t)i * d, Gt + (size_t)i * d, &sc, &nza);
                 gn[i] = nrm2(d, Gt + (size_t)i * d);
             }
             scratch_free(&sc);
@@ -1097,7 +1194,7 @@ int orc_cycle(const orc_problem *P, const double *logc, const orc_config *C, orc
     S->K_lost = 0; S->reseed_kind = 0; S->sigma = 0.0; S->alpha_c = 0.0; S->alpha_a = 0.0;
     S->n_free = 0; S->n_unfrozen = 0;
     if ((rc = orc_phase_converge(P, logc, C, S, R))) return rc;
-    if ((rc = orc_phase_stick(P, C, S, R))) return rc;
+    if ((rc = orc_phase_stick(P, logc, C, S, R))) return rc;
     if ((rc = orc_phase_dedup(P, C, S, R))) return rc;
     if (!last) {
         if ((rc = orc_phase_reseed(P, C, S))) return rc;

@@ -61,7 +61,8 @@ class _State(C.Structure):
                 ("gr_used_last", C.c_int32), ("gr_prev_modes", C.c_int32), ("f_max", C.c_double),
                 ("sigma", C.c_double), ("alpha_c", C.c_double), ("alpha_a", C.c_double),
                 ("K_lost", C.c_int32), ("n_stuck", C.c_int32), ("n_modes", C.c_int32),
-                ("reseed_kind", C.c_int32), ("n_free", C.c_int32), ("n_unfrozen", C.c_int32)]
+                ("reseed_kind", C.c_int32), ("n_free", C.c_int32), ("n_unfrozen", C.c_int32),
+                ("Fg", C.c_void_p)]
 
 
 class _Replay(C.Structure):
@@ -95,7 +96,7 @@ def lib():
             getattr(L, name).argtypes = [P(_Problem), C.c_void_p, P(_Config), P(_State), P(_Replay)]
         L.orc_lbfgs_iterate.argtypes = [P(_Problem), C.c_void_p, P(_Config), P(_State), C.c_int, C.c_int,
                                         P(_Replay)]
-        L.orc_phase_stick.argtypes = [P(_Problem), P(_Config), P(_State), P(_Replay)]
+        L.orc_phase_stick.argtypes = [P(_Problem), C.c_void_p, P(_Config), P(_State), P(_Replay)]
         L.orc_phase_dedup.argtypes = [P(_Problem), P(_Config), P(_State), P(_Replay)]
         L.orc_phase_reseed.argtypes = [P(_Problem), P(_Config), P(_State)]
         L.orc_phase_hlc.argtypes = [P(_Problem), C.c_void_p, P(_Config), P(_State)]
@@ -206,9 +207,11 @@ class OracleRun:
         self.head = np.full(N, m - 1, np.int32)
         self.cnt = np.zeros(N, np.int32)
         self.trace = np.full((cfg.n_conv + 1, N), TR_NONE, np.uint8)
+        self.Fg = np.zeros(N)
         self.st = _State(_ptr(self.X), _ptr(self.F), _ptr(self.G), _ptr(self.V), _ptr(self.stuck),
                          _ptr(self.active), _ptr(self.conv), _ptr(self.removed), _ptr(self.S), _ptr(self.Y),
                          _ptr(self.rho), _ptr(self.head), _ptr(self.cnt), 0, 0, 0, 0, 0)
+        self.st.Fg = _ptr(self.Fg)
 
     @property
     def k(self) -> int:
@@ -267,7 +270,8 @@ class OracleRun:
 
     def phase_stick(self, **replay) -> ReplayReport:
         r = self._replay(**replay)
-        self._check(lib().orc_phase_stick(C.byref(self.P.c), C.byref(self.cc), C.byref(self.st), C.byref(r)),
+        self._check(lib().orc_phase_stick(C.byref(self.P.c), _ptr(self.P.logc), C.byref(self.cc), C.byref(self.st),
+                                          C.byref(r)),
                     "stick")
         return self._report(r)
 
@@ -289,8 +293,10 @@ class OracleRun:
                                          C.byref(self.st)), "anti")
 
     def modes(self):
+        """Stuck active samples, their values (gate values when noisy) and indices."""
         idx = np.nonzero(self.stuck & self.active)[0]
-        return self.X[idx].copy(), self.F[idx].copy(), idx
+        fv = self.Fg if self.P.noise_sigma > 0 else self.F
+        return self.X[idx].copy(), fv[idx].copy(), idx
 
     def stats(self) -> dict:
         s = self.st

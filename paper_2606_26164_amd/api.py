@@ -156,8 +156,8 @@ class Optimizer:
         if history:
             out.update(S=np.zeros((N, m, d), np.float32), Y=np.zeros((N, m, d), np.float32),
                        rho=np.zeros((N, m), np.float32), head=np.zeros(N, np.int32), cnt=np.zeros(N, np.int32),
-                       conv=np.zeros(N, np.uint8))
-            for f in ("S", "Y", "rho", "head", "cnt", "conv"):
+                       conv=np.zeros(N, np.uint8), Fg=np.zeros(N, np.float32))
+            for f in ("S", "Y", "rho", "head", "cnt", "conv", "Fg"):
                 setattr(s, f, out[f].ctypes.data)
         L.check(self.lib.chisao_get_state(self.h, problem, C.byref(s)), "chisao_get_state")
         out.update(k=s.k, gr_disabled=s.gr_disabled, gr_fail=s.gr_fail, gr_used_last=s.gr_used_last,

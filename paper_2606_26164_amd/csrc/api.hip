@@ -85,6 +85,7 @@ struct chisao_ctx {
     int device = 0;
     int k_host = 0;  // cycles completed
     uint32_t flags = 0;
+    bool any_noise = false;
     std::vector<ProblemDesc> pdh;  // host copy of the descriptors
     std::vector<EvalClass> eclasses;
     std::vector<LbfgsClass> lclasses;
@@ -138,8 +139,8 @@ static int validate(const chisao_problem *p, const chisao_config *c, int idx) {
         return fail(CHISAO_E_INVAL, "problem %d: null problem array", idx);
     if (p->family == CHISAO_STUDENT_T && !(p->nu > 0.0f && isfinite(p->nu)))
         return fail(CHISAO_E_INVAL, "problem %d: Student-t needs nu > 0", idx);
-    if (p->noise_sigma != 0.0f)
-        return fail(CHISAO_E_INVAL, "problem %d: noisy objectives are not supported in this version", idx);
+    if (!(p->noise_sigma >= 0.0f && isfinite(p->noise_sigma)))
+        return fail(CHISAO_E_INVAL, "problem %d: noise_sigma must be finite and >= 0", idx);
     const int d = p->d, K = p->K;
     for (int j = 0; j < d; ++j)
         if (!(isfinite(p->lo[j]) && isfinite(p->hi[j]) && p->lo[j] < p->hi[j]))
@@ -165,7 +166,7 @@ static int validate(const chisao_problem *p, const chisao_config *c, int idx) {
     if (c->ls_max < 1 || c->ls_max > 16) return fail(CHISAO_E_INVAL, "problem %d: ls_max must be in 1..16", idx);
     if (c->grad_mode != CHISAO_GRAD_FD && c->grad_mode != CHISAO_GRAD_ADJOINT)
         return fail(CHISAO_E_INVAL, "problem %d: unknown grad_mode", idx);
-    if (c->gate_reps != 0) return fail(CHISAO_E_INVAL, "problem %d: gate_reps is reserved and must be 0", idx);
+    if (c->gate_reps < 0 || c->gate_reps > 4096) return fail(CHISAO_E_INVAL, "problem %d: gate_reps must be in 0..4096", idx);
     if (!(c->eps_grad > 0.0f) || !(c->eps_dup > 0.0f))
         return fail(CHISAO_E_INVAL, "problem %d: eps_grad and eps_dup must be > 0", idx);
     if (!isfinite(c->log_delta) || !isfinite(c->momentum) || !isfinite(c->alpha) || !isfinite(c->sigma) ||
@@ -322,6 +323,9 @@ extern "C" int chisao_init_batched(chisao_handle *out, int n_problems, const chi
             q.key0 = (uint32_t)(c.seed & 0xFFFFFFFFu);
             q.key1 = (uint32_t)(c.seed >> 32) ^ c.problem_id;
             q.phase_mask = c.phase_mask;
+            q.noise_sigma = pr.noise_sigma;
+            q.gate_reps = c.gate_reps > 0 ? c.gate_reps : c.M;
+            h->any_noise |= pr.noise_sigma > 0.0f;
         }
         ProblemDesc *pd_dev;
         ALLOC(pd_dev, ProblemDesc, P);
@@ -381,6 +385,7 @@ extern "C" int chisao_init_batched(chisao_handle *out, int n_problems, const chi
         ALLOC(D.Pd, float, N * DSz);
         ALLOC(D.Gh, float, N * DSz);
         ALLOC(D.ginf, float, N);
+        ALLOC(D.Fg, float, N);
         if (any_fd) ALLOC(D.Gp, float, N * (size_t)Mmax * DSz);
         ALLOC(D.stuck, uint8_t, N);
         ALLOC(D.active, uint8_t, N);
@@ -481,6 +486,7 @@ static EvalArgs base_args(chisao_ctx *h, const EvalClass &c) {
     a.ext_n = -1;
     a.list_id = -1;
     a.trial_next = -1;
+    a.nz_kind = -1;
     return a;
 }
 
@@ -504,9 +510,11 @@ static hipError_t run_eval(chisao_ctx *h, const EvalClass &c, EvalArgs &a, int c
 }
 
 // value and gradient of the samples on a list: adjoint in one pass; with
-// finite differences the value (if wanted) and the stencil gradient
+// finite differences the value (if wanted) and the stencil gradient.  Values
+// of noisy problems carry noise (sub-stream 0 for the value, fd_base plus the
+// stencil index for the differences).
 static hipError_t eval_list(chisao_ctx *h, int list_id, float *F_out, float *G_out, bool want_f, int need_bit,
-                            int step_limit, int step) {
+                            int step_limit, int step, uint32_t fd_base) {
     for (const EvalClass &c : h->eclasses) {
         EvalArgs a = base_args(h, c);
         a.list_id = list_id;
@@ -514,6 +522,8 @@ static hipError_t eval_list(chisao_ctx *h, int list_id, float *F_out, float *G_o
         a.need_bit = need_bit;
         a.step_limit = step_limit;
         a.step = step;
+        a.nz_kind = 0;
+        a.nz_base = 0;
         hipError_t e;
         if (c.grad_mode == CHISAO_GRAD_ADJOINT) {
             a.F_out = F_out;
@@ -528,6 +538,7 @@ static hipError_t eval_list(chisao_ctx *h, int list_id, float *F_out, float *G_o
         }
         a.F_out = nullptr;
         a.G_out = G_out;
+        a.nz_base = fd_base;
         if ((e = run_eval(h, c, a, kDirect, true, false)) != hipSuccess) return e;
     }
     return hipSuccess;
@@ -538,7 +549,7 @@ static hipError_t phase_converge(chisao_ctx *h) {
     hipStream_t st = h->cur;
     hipError_t e;
     if ((e = launch_begin_cycle(D, st)) != hipSuccess) return e;
-    if ((e = eval_list(h, L_ACT, D.F, D.G, true, 0, 0, 0)) != hipSuccess) return e;
+    if ((e = eval_list(h, L_ACT, D.F, D.G, true, 0, 0, 0, kNzFd1)) != hipSuccess) return e;
     for (int t = 1; t <= D.n_conv_max + 1; ++t) {
         // the steppers of iteration t go to list_out; t+1 reads them back
         const int list_in = t == 1 ? L_ACT : ((t - 1) % 2 ? L_T1 : L_T1B);
@@ -558,6 +569,8 @@ static hipError_t phase_converge(chisao_ctx *h) {
             a.list_id = list_out;
             a.vc_kind = kVcTrialFirst;
             a.trial_next = L_T2;
+            a.step = t;
+            a.nz_kind = 0;
             if ((e = run_eval(h, c, a, kTrial, false, c.grad_mode == CHISAO_GRAD_ADJOINT)) != hipSuccess) return e;
         }
         if ((e = launch_compact(D, list_out, L_T2, L_FD, true, nullptr, st)) != hipSuccess) return e;
@@ -566,6 +579,8 @@ static hipError_t phase_converge(chisao_ctx *h) {
             a.list_id = L_T2;
             a.vc_kind = kVcTrialRest;
             a.trial_next = -1;
+            a.step = t;
+            a.nz_kind = 0;
             if ((e = run_eval(h, c, a, kTrial, false, c.grad_mode == CHISAO_GRAD_ADJOINT)) != hipSuccess) return e;
         }
         if ((e = launch_compact(D, L_T2, -1, L_FD, true, nullptr, st)) != hipSuccess) return e;
@@ -575,9 +590,22 @@ static hipError_t phase_converge(chisao_ctx *h) {
             b.list_id = L_FD;
             b.vc_kind = kVcOne;
             b.G_out = D.G;
+            b.step = t;
+            b.nz_kind = 0;
+            b.nz_base = kNzFd1;
             if ((e = run_eval(h, c, b, kDirect, true, false)) != hipSuccess) return e;
         }
     }
+    // quality-gate values of noisy problems (the other problems have no jobs)
+    if (h->any_noise)
+        for (const EvalClass &c : h->eclasses) {
+            EvalArgs a = base_args(h, c);
+            a.list_id = L_ACT;
+            a.vc_kind = kVcOne;
+            a.F_out = D.Fg;
+            a.nz_kind = 1;
+            if ((e = run_eval(h, c, a, kDirect, false, false)) != hipSuccess) return e;
+        }
     return hipSuccess;
 }
 
@@ -603,6 +631,8 @@ static hipError_t phase_hlc(chisao_ctx *h) {
             a.step = step;
             a.need_bit = 1 << 5;
             a.step_limit = 1;
+            a.nz_kind = adj ? -1 : 0;
+            a.nz_base = kNzFdProbe;
             if ((e = run_eval(h, c, a, kProbe, !adj, adj)) != hipSuccess) return e;
         }
         if ((e = launch_probe_mean(D, step, st)) != hipSuccess) return e;
@@ -618,7 +648,7 @@ static hipError_t phase_anti(chisao_ctx *h) {
     hipError_t e;
     const int n_anti = max_over(h, &ProblemDesc::n_anti);
     for (int step = 0; step < n_anti; ++step) {
-        if ((e = eval_list(h, L_UNF, nullptr, D.Gh, false, 1 << 6, 2, step)) != hipSuccess) return e;
+        if ((e = eval_list(h, L_UNF, nullptr, D.Gh, false, 1 << 6, 2, step, kNzFdAnti)) != hipSuccess) return e;
         if (step == 0 && (e = launch_step_size(D, D.Gh, 1, st)) != hipSuccess) return e;
         if ((e = launch_anti_update(D, step, st)) != hipSuccess) return e;
     }
@@ -778,6 +808,7 @@ extern "C" int chisao_get_state(chisao_handle h, int problem, chisao_state *s) {
     if (s->head) HIP_TRY(hipMemcpy(s->head, D.head + s0, sizeof(int) * N, hipMemcpyDeviceToHost));
     if (s->cnt) HIP_TRY(hipMemcpy(s->cnt, D.cnt + s0, sizeof(int) * N, hipMemcpyDeviceToHost));
     if (s->conv) HIP_TRY(hipMemcpy(s->conv, D.conv + s0, N, hipMemcpyDeviceToHost));
+    if (s->Fg) HIP_TRY(hipMemcpy(s->Fg, D.Fg + s0, sizeof(float) * N, hipMemcpyDeviceToHost));
     Ctl c;
     HIP_TRY(hipMemcpy(&c, D.ctl + problem, sizeof c, hipMemcpyDeviceToHost));
     s->k = c.k;

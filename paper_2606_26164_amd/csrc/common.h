@@ -14,7 +14,7 @@ constexpr int kWave = 64;
 // (index, cycle, consumer << 24 | step << 16 | sub, block); the key is the
 // 64-bit seed with the problem id folded into the high word.
 // ---------------------------------------------------------------------------
-enum Stream : uint32_t { kInit = 0, kRM = 4, kGR = 5, kHLC = 6 };
+enum Stream : uint32_t { kInit = 0, kRM = 4, kGR = 5, kHLC = 6, kNoise = 7, kGate = 8 };
 
 __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
                                         uint32_t k1) {
@@ -137,6 +137,8 @@ struct ProblemDesc {
     int m, n_conv, n_anti, n_cloud, M, ls_max, grad_mode;
     float eps_grad, eps_dup, log_delta, momentum, alpha, sigma_cfg, sigma_c, fd_h, ls_c1, curv_eps;
     uint32_t key0, key1, phase_mask;
+    float noise_sigma;  // additive evaluation noise (0: none)
+    int gate_reps;      // noisy evaluations averaged by the quality gate
 };
 
 // ---------------------------------------------------------------------------
@@ -188,6 +190,7 @@ struct Dev {
     const uint16_t *pid;     // [NT] problem of each sample
     // population state (rows of stride DS)
     float *X, *F, *G, *V, *Xprev, *Gprev, *Pd, *Gh, *Gp, *ginf;
+    float *Fg;  // quality-gate values of noisy problems
     uint8_t *stuck, *active, *conv, *removed, *stuck_pre, *status, *reset, *steep, *trace;
     float *S, *Y, *rho;      // [NT][mmax][DS], [NT][mmax]
     int *head, *cnt;
@@ -201,6 +204,18 @@ struct Dev {
 };
 
 __device__ __forceinline__ int *list_ptr(const Dev &D, int id, int s0) { return D.lists + (size_t)id * D.NT + s0; }
+
+// The values the quality gate, the deduplication order and the mode output
+// use: f as the search saw it, or the gate values of a noisy problem.
+__device__ __forceinline__ const float *gate_values(const Dev &D, const ProblemDesc &pd) {
+    return pd.noise_sigma > 0.0f ? D.Fg : D.F;
+}
+
+// Noise sub-stream offsets (low 16 bits of the third counter word): the
+// centre value 0, line-search trial r, and these bases plus the stencil index
+// for central differences in Phase 1, smoothing probes (| probe << 7) and
+// anti-convergence.
+constexpr uint32_t kNzFd1 = 0x1000, kNzFdProbe = 0x2000, kNzFdAnti = 0x3000;
 
 // Lanes with `want` each take one unit of a per-problem counter (counter(p)
 // gives its address): one atomic per distinct problem among the wave's lanes

@@ -318,7 +318,8 @@ __global__ __launch_bounds__(kBlock) void lbfgs_step_kernel(Dev D, int t, int li
                 }
                 const bool converged = gi < pd.eps_grad;
                 if (converged) code |= kTrConv;
-                const bool stall = !converged && !accepted && D.steep[s];
+                // (with evaluation noise a repeated search draws fresh values)
+                const bool stall = !converged && !accepted && D.steep[s] && !(pd.noise_sigma > 0.0f);
                 done = converged || stall;
                 if (l16 == 0) {
                     D.ginf[s] = gi;
@@ -438,7 +439,7 @@ __global__ void fmax_kernel(Dev D) {
     float v = -INFINITY;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < pd.N; i += gridDim.x * blockDim.x) {
         const int s = pd.s0 + i;
-        if (D.active[s]) v = fmaxf(v, D.F[s]);
+        if (D.active[s]) v = fmaxf(v, gate_values(D, pd)[s]);
     }
     red[threadIdx.x] = v;
     __syncthreads();
@@ -458,7 +459,7 @@ __global__ void stick_kernel(Dev D) {
     for (int b = blockIdx.x * blockDim.x; b < pd.N; b += gridDim.x * blockDim.x) {
         const int i = b + threadIdx.x, s = pd.s0 + i;
         const bool act = i < pd.N && D.active[s];
-        const bool st = act && (D.ginf[s] < pd.eps_grad) && (D.F[s] >= gate);
+        const bool st = act && (D.ginf[s] < pd.eps_grad) && (gate_values(D, pd)[s] >= gate);
         if (act) D.stuck_pre[s] = st;
         wave_append(D, L_STK, st, p, s);
         wave_claim(st, p, [&](int q) { return &D.ctl[q].n_stuck; });
@@ -495,7 +496,8 @@ __global__ __launch_bounds__(kBlock) void dedup_kernel(Dev D) {
         const int jj = base + threadIdx.x;
         const int j = jj < ns ? lst[jj] : -1;
         const float xj0 = j >= 0 ? D.X[(size_t)j * DS] : 0.0f;
-        const float fj = j >= 0 ? D.F[j] : 0.0f;
+        const float *Fv = gate_values(D, pd);
+        const float fj = j >= 0 ? Fv[j] : 0.0f;
         bool rem = false;
         for (int tb = 0; tb < ns; tb += kBlock) {
             __syncthreads();
@@ -504,7 +506,7 @@ __global__ __launch_bounds__(kBlock) void dedup_kernel(Dev D) {
                 const int i = lst[ii];
                 t_i[threadIdx.x] = i;
                 t_x0[threadIdx.x] = D.X[(size_t)i * DS];
-                t_f[threadIdx.x] = D.F[i];
+                t_f[threadIdx.x] = Fv[i];
             }
             __syncthreads();
             const int nt = min(kBlock, ns - tb);
@@ -1046,7 +1048,7 @@ __global__ void gather_modes_kernel(Dev D, int p) {
         const int j = (int)(e / pd.d), c = (int)(e % pd.d);
         const int s = lst[j];
         xo[(size_t)j * pd.d + c] = D.X[(size_t)s * D.DS + c];
-        if (c == 0) D.Pd[pd.s0 + j] = D.F[s];
+        if (c == 0) D.Pd[pd.s0 + j] = gate_values(D, pd)[s];
     }
 }
 

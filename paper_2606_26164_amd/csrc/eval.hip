@@ -64,6 +64,7 @@ constexpr int kMaxClass = 256;  // problems per class (LDS budget: 2 waves per S
 
 __device__ __forceinline__ int job_count(const EvalArgs &a, int p, const ProblemDesc &pd) {
     if (a.ext_n >= 0) return a.ext_n;
+    if (a.nz_kind == 1 && !(pd.noise_sigma > 0.0f)) return 0;
     if (a.need_bit && !(pd.phase_mask & (uint32_t)a.need_bit)) return 0;
     if ((a.step_limit == 1 && a.step >= pd.n_cloud) || (a.step_limit == 2 && a.step >= pd.n_anti)) return 0;
     return a.list_id >= 0 ? a.D.ctl[p].count[a.list_id] : pd.N;
@@ -335,10 +336,36 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void
             step(rb);
         }
         // ---- results to LDS ------------------------------------------------
+        // Noisy problems: every value the method sees carries sigma_n z, z the
+        // first normal of the NOISE stream at (sample, cycle, step << 16 |
+        // sub); the gate value carries sigma_n times the mean of gate_reps
+        // normals of the GATE stream.  The gradient stays noise-free.
+        const bool noisy = !ext && a.nz_kind >= 0 && pd.noise_sigma > 0.0f;
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
             const int pt = nb * 16 + n;
-            const float f = (mrun[nb] + __log2f(srun[nb])) * kLn2;
+            float f = (mrun[nb] + __log2f(srun[nb])) * kLn2;
+            if (noisy && g == 0 && s_s[pt] >= 0) {
+                const uint32_t ls = (uint32_t)(s_s[pt] - pd.s0);
+                if (a.nz_kind == 0) {
+                    uint32_t sub = a.nz_base;
+                    if constexpr (CENTER == kTrial) sub += (uint32_t)(r0 + s_c[pt]);
+                    if constexpr (CENTER == kProbe) sub |= (uint32_t)s_c[pt] << 7;
+                    if constexpr (FD) sub += (uint32_t)s_st[pt];
+                    float z[4];
+                    box_muller4(philox(ls, kcyc, (kNoise << 24) | ((uint32_t)a.step << 16) | sub, 0u, pd.key0, pd.key1),
+                                z);
+                    f += pd.noise_sigma * z[0];
+                } else {
+                    float zs = 0.0f;
+                    for (int b = 0; 4 * b < pd.gate_reps; ++b) {
+                        float z[4];
+                        box_muller4(philox(ls, kcyc, kGate << 24, (uint32_t)b, pd.key0, pd.key1), z);
+                        for (int q = 0; q < 4 && 4 * b + q < pd.gate_reps; ++q) zs += z[q];
+                    }
+                    f += pd.noise_sigma * (zs / (float)pd.gate_reps);
+                }
+            }
             if (g == 0) s_f[pt] = f;
             if constexpr (GRAD) {
                 const float inv = -1.0f / srun[nb];
@@ -391,7 +418,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void
                     for (int c = h; c < d; c += 2)
                         dot += D.G[(size_t)s * DS + c] * (s_pts[pt * LD + c] - D.X[(size_t)s * DS + c]);
                 dot += __shfl_xor(dot, 1, kWave);
-                if (h == 0) s_pass[pt] = (s >= 0) && (s_f[pt] - D.F[s] - pd.ls_c1 * dot >= 0.0f);
+                // (relaxed by twice the noise level for noisy objectives: the
+                // noise-aware Armijo test of Berahas, Byrd and Nocedal 2019)
+                if (h == 0)
+                    s_pass[pt] = (s >= 0) && (s_f[pt] - D.F[s] - pd.ls_c1 * dot + 2.0f * pd.noise_sigma >= 0.0f);
             }
             __syncthreads();
             if (lane < jpw) {

@@ -26,13 +26,15 @@ struct EvalArgs {
     int ext_n;            // >= 0: caller memory, jobs 0..ext_n-1 of problem cls[0]; -1: population lists
     int list_id;          // population jobs: list id, or -1 for every sample of the problem
     int vc_kind;          // VcKind
-    int step;             // smoothing step index (probe stream)
+    int step;             // step index: smoothing/anti step, L-BFGS iteration (noise stream)
     float *F_out;         // direct centres: value per job row (may be null)
     float *G_out;         // direct centres: gradient rows (may be null)
     int out_stride;
     int trial_next;       // trial centres: list receiving rejected samples (-1: mark failed)
     int need_bit;         // phase_mask bit a problem must have set to take part (0: none)
     int step_limit;       // 1: only problems with step < n_cloud, 2: step < n_anti, 0: all
+    int nz_kind;          // evaluation noise of noisy problems: -1 none, 0 one draw per value, 1 gate mean
+    uint32_t nz_base;     // noise sub-stream base (kind 0); the noise step is `step`
 };
 
 // center: kDirect / kTrial / kProbe; fd: stencil around each centre;

@@ -1,0 +1,125 @@
+"""Noisy objectives on the GPU against the FP64 oracle: every evaluation
+carries sigma_n z from the NOISE stream (the same counters on both sides, so
+the draws agree up to the FP32 Box-Muller rounding), the analytic gradient is
+exact, and the quality gate uses the mean of R fresh noisy evaluations."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import oracle as O
+
+from test_gpu_phases import REPLAY, _gpu, _oracle_from, _rows_close
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(grad_mode=1, N=256, n_conv=10, sigma=0.5, family=W.STUDENT_T):
+    p = W.mixture_problem(41, 12, 8, 4.0, lam_range=(0.3, 1.0), family=family, nu=3.0, noise_sigma=sigma)
+    c = W.RunConfig(N=N, m=6, n_osc=3, n_conv=n_conv, M=8, eps_grad=1e-3, grad_mode=grad_mode, gate_reps=16,
+                    seed=6)
+    return p, c, W.uniform_population(41, N, p.lo, p.hi)
+
+
+def test_noisy_phase1_adjoint_parity_with_replay():
+    """Gaussian mixture (well conditioned everywhere), all of Phase 1."""
+    prob, cfg, x0 = _case(family=W.GAUSS)
+    with _gpu(prob, cfg, x0) as opt:
+        opt.run_phases(1 << 1)
+        g = opt.get_state(history=True)
+    run = O.OracleRun(prob, cfg, x0)
+    rep = run.phase_converge(trace_in=g["trace"], **REPLAY)
+    print(f"\ndecisions {rep.n_decisions} borderline by kind {rep.border_by_kind} hard {rep.n_hard}")
+    assert rep.n_hard == 0, rep
+    # no stall shortcut under noise: a repeated search draws fresh values
+    assert not (g["conv"] == 2).any()
+    np.testing.assert_array_equal(g["trace"] != O.TR_NONE, run.trace != O.TR_NONE)
+    _rows_close(g["X"], run.X, 1e-4, "X after phase 1")
+    # the line-search value carries the noise of the accepted trial
+    _rows_close(g["F"][:, None], run.F[:, None], 1e-4, "noisy F after phase 1")
+    # the gradient is the exact one at the GPU's positions
+    f_at, G_at = run.P.eval(g["X"].astype(np.float64))
+    _rows_close(g["G"], G_at, 1e-4, "G after phase 1")
+    assert np.abs(g["F"] - f_at).max() > 0.1  # the values are noisy
+
+
+@pytest.mark.parametrize("t", [1, 3, 7])
+def test_noisy_student_t_single_iteration_parity(t):
+    """Student-t tails are flat far from the centres, so the first scaling
+    s'y/y'y is large and FP32 directions differ from FP64 ones by more than
+    1e-4 after a few steps: the oracle continues from the GPU's own state
+    after t iterations and must reproduce iteration t+1."""
+    prob, cfg, x0 = _case()
+    with _gpu(prob, cfg.with_(n_conv=t), x0) as opt:
+        opt.run_phases(1 << 1)
+        a = opt.get_state(history=True)
+    with _gpu(prob, cfg.with_(n_conv=t + 1), x0) as opt:
+        opt.run_phases(1 << 1)
+        b = opt.get_state(history=True)
+    run = _oracle_from(prob, cfg.with_(n_conv=t + 1), a)
+    for f in ("S", "Y", "rho", "head", "cnt"):
+        getattr(run, f)[:] = a[f]
+    run.conv[:] = a["conv"] == 1
+    rep = run.iterate(t + 1, 1, trace_in=b["trace"], **REPLAY)
+    print(f"\nt={t}: borderline {rep.border_by_kind} hard {rep.n_hard}")
+    assert rep.n_hard == 0, rep
+    _rows_close(b["X"], run.X, 1e-4, f"X after iteration {t + 1}")
+    _rows_close(b["F"][:, None], run.F[:, None], 1e-4, f"noisy F after iteration {t + 1}")
+
+
+def test_noisy_gate_values_and_stick_parity():
+    prob, cfg, x0 = _case(N=512, n_conv=25, sigma=0.3)
+    with _gpu(prob, cfg, x0) as opt:
+        opt.run_phases(1 << 1)
+        g1 = opt.get_state(history=True)
+        opt.run_phases((1 << 2) | (1 << 3))
+        g3 = opt.get_state()
+    run = _oracle_from(prob, cfg, g1)
+    r2 = run.phase_stick(stuck_in=g3["stuck_pre"], **REPLAY)
+    print(f"\nstuck {int(g3['stuck_pre'].sum())}, stick replay {r2}")
+    assert r2.n_hard == 0
+    assert g3["stuck_pre"].sum() > 0
+    act = g1["active"] == 1
+    _rows_close(g1["Fg"][act][:, None], run.Fg[act][:, None], 1e-5, "gate values")
+    r3 = run.phase_dedup(removed_in=g3["removed"], **REPLAY)
+    assert r3.n_hard == 0
+    np.testing.assert_array_equal(run.stuck, g3["stuck"])
+
+
+def test_noisy_fd_first_iteration_parity():
+    """Central differences of noisy values: the stencil draws (two per
+    coordinate) must be the oracle's, or the first step moves elsewhere."""
+    prob, cfg, x0 = _case(grad_mode=0, N=128, n_conv=1, sigma=0.05, family=W.GAUSS)
+    cfg = cfg.with_(fd_h=1e-2)
+    with _gpu(prob, cfg, x0) as opt:
+        opt.run_phases(1 << 1)
+        g = opt.get_state()
+    run = O.OracleRun(prob, cfg, x0)
+    rep = run.phase_converge(trace_in=g["trace"], **REPLAY)
+    assert rep.n_hard == 0, rep
+    # FP32 differences of values ~1e1 over 2h = 2e-2: ~1e-4 relative rounding
+    _rows_close(g["X"], run.X, 2e-3, "X after one noisy FD iteration")
+    _rows_close(g["G"], run.G, 2e-2, "noisy FD gradient", floor=10.0)
+
+
+def test_config5_shape_full_run_modes_are_maxima():
+    """Student-t mixture with unit noise at the config-5 shape (d=32, K=48,
+    M=32 probes at sigma=0.2, gate over 32 draws), a reduced population and
+    schedule: every recovered point is a distinct local maximum of the
+    noise-free objective, and the run's gate is self-consistent."""
+    from oracle.modes import newton_modes
+    from paper_2606_26164_amd.api import Optimizer
+
+    prob, cfg, x0 = W.config5(N=16384, n_osc=40)
+    Xall, Fall = newton_modes(prob, log_delta=None)
+    with Optimizer(prob, cfg, x0) as opt:
+        stats = opt.cycle(cfg.n_osc, stats=True)
+        ms = opt.modes()
+    X = ms.X.astype(np.float64)
+    print(f"\n{len(X)} modes; {len(Xall)} local maxima; f_max {stats[-1]['f_max']:.3f}; "
+          f"stuck {stats[-1]['n_stuck']}")
+    assert len(X) >= 1
+    for x in X:
+        dist = np.abs(Xall - x).max(1)
+        assert dist.min() < 1e-2, dist.min()
+    assert len(set(int(np.argmin(np.abs(Xall - x).max(1))) for x in X)) == len(X)
+    assert ms.F.min() >= stats[-1]["f_max"] + cfg.log_delta - 1e-5
