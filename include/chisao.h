@@ -94,7 +94,8 @@ typedef struct {
     uint32_t flags;     /* CHISAO_FLAG_* (handle-wide; taken from the first problem of a batch) */
 } chisao_config;
 
-#define CHISAO_FLAG_NO_GRAPH 1u /* enqueue every cycle's kernels one by one instead of replaying a captured hipGraph */
+#define CHISAO_FLAG_NO_GRAPH 1u    /* enqueue every cycle's kernels one by one instead of replaying a captured hipGraph */
+#define CHISAO_FLAG_NO_AUTOTUNE 2u /* keep the default evaluation schedule (linear tile order, 8192 workgroups) */
 
 /* Per-cycle statistics (host struct). */
 typedef struct {
@@ -218,6 +219,27 @@ void chisao_destroy(chisao_handle h);
 /* Message of the last failure on this thread ("" if none); valid until the
  * next library call on the same thread. */
 const char *chisao_last_error(void);
+
+/* Evaluation launch schedules chosen at init.  Problems are grouped into
+ * classes by (padded d, family, gradient mode); for each class the autotuner
+ * times CHISAO_TUNE_VARIANTS schedules on a value+gradient pass over the
+ * starting population and keeps the fastest: variant v uses tile order v % 2
+ * (0 linear, 1 XCD-chunked) and a grid of 8192 (v < 2) or 1024 workgroups.
+ * The schedule changes timing only, never results. */
+#define CHISAO_TUNE_VARIANTS 4
+typedef struct {
+    int32_t padded_d;    /* 16, 32 or 64 */
+    int32_t family;
+    int32_t grad_mode;
+    int32_t n_problems;  /* problems in the class */
+    int32_t order;       /* chosen tile order */
+    int32_t grid_cap;    /* chosen grid size */
+    float ms[CHISAO_TUNE_VARIANTS]; /* measured time per variant (0 when not tuned) */
+} chisao_tuning_entry;
+
+/* Writes one entry per class (at most cap) and the class count to *n_out;
+ * cap too small: CHISAO_E_RANGE with *n_out set.  Host memory. */
+int chisao_tuning(chisao_handle h, chisao_tuning_entry *out, int cap, int *n_out);
 
 #ifdef __cplusplus
 }

@@ -11,6 +11,8 @@ OK, E_INVAL, E_NOMEM, E_DEVICE, E_STATE, E_RANGE = 0, -1, -2, -3, -4, -5
 GAUSS, STUDENT_T = 0, 1
 GRAD_FD, GRAD_ADJOINT = 0, 1
 FLAG_NO_GRAPH = 1
+FLAG_NO_AUTOTUNE = 2
+TUNE_VARIANTS = 4
 
 
 class Problem(C.Structure):
@@ -44,6 +46,12 @@ class State(C.Structure):
                 ("head", C.c_void_p), ("cnt", C.c_void_p), ("conv", C.c_void_p), ("Fg", C.c_void_p)]
 
 
+class TuningEntry(C.Structure):
+    _fields_ = [("padded_d", C.c_int32), ("family", C.c_int32), ("grad_mode", C.c_int32),
+                ("n_problems", C.c_int32), ("order", C.c_int32), ("grid_cap", C.c_int32),
+                ("ms", C.c_float * 4)]
+
+
 class KernelProfile(C.Structure):
     _fields_ = [("launches", C.c_int32), ("ms", C.c_double), ("points", C.c_int64)]
 
@@ -52,7 +60,7 @@ PROF_CLASSES = 8
 PROF_NAMES = ("eval_direct", "eval_trial", "eval_probe", "eval_fd", "lbfgs", "unused5", "unused6", "unused7")
 
 EXPORTS = ("chisao_init", "chisao_init_batched", "chisao_profile", "chisao_cycle", "chisao_modes", "chisao_get_state", "chisao_set_state",
-           "chisao_run_phases", "chisao_eval", "chisao_destroy", "chisao_last_error")
+           "chisao_run_phases", "chisao_eval", "chisao_destroy", "chisao_last_error", "chisao_tuning")
 
 _lib = None
 
@@ -86,6 +94,8 @@ def load(path: str = LIB_PATH):
     L.chisao_profile.restype = C.c_int
     L.chisao_destroy.argtypes = [C.c_void_p]
     L.chisao_destroy.restype = None
+    L.chisao_tuning.argtypes = [C.c_void_p, P(TuningEntry), C.c_int, P(C.c_int)]
+    L.chisao_tuning.restype = C.c_int
     L.chisao_last_error.argtypes = []
     L.chisao_last_error.restype = C.c_char_p
     _lib = L

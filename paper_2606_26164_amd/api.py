@@ -132,6 +132,14 @@ class Optimizer:
         return {L.PROF_NAMES[i]: dict(launches=arr[i].launches, ms=arr[i].ms, points=arr[i].points)
                 for i in range(L.PROF_CLASSES) if arr[i].launches or arr[i].points}
 
+    def tuning(self) -> list:
+        """The evaluation schedule the autotuner chose for each problem class."""
+        arr = (L.TuningEntry * 64)()
+        n = C.c_int(0)
+        L.check(self.lib.chisao_tuning(self.h, arr, 64, C.byref(n)), "chisao_tuning")
+        return [dict(padded_d=e.padded_d, family=e.family, grad_mode=e.grad_mode, n_problems=e.n_problems,
+                     order=e.order, grid_cap=e.grid_cap, ms=list(e.ms)) for e in arr[:n.value]]
+
     def run_phases(self, mask: int):
         L.check(self.lib.chisao_run_phases(self.h, mask), "chisao_run_phases")
 

@@ -60,6 +60,13 @@ struct Buffers {
 };
 
 int pad_dim(int d) { return d <= 16 ? 16 : (d <= 32 ? 32 : 64); }
+
+// Launch schedules the autotuner tries per evaluation class: tile order
+// (linear, XCD-chunked) x grid (8192 workgroups, dispatched as slots free up;
+// 1024, one resident wave per SIMD looping over tiles).
+constexpr int kTuneVariants = 4;
+constexpr int kTuneOrder[kTuneVariants] = {0, 1, 0, 1};
+constexpr int kTuneCap[kTuneVariants] = {8192, 8192, 1024, 1024};
 int coords_per_lane(int d) { return d <= 16 ? 1 : (d <= 32 ? 2 : 4); }
 
 }  // namespace
@@ -69,6 +76,8 @@ struct EvalClass {
     int DP, family, grad_mode;
     const int *pids_dev;  // into the handle's class table
     std::vector<int> pids;
+    int order = 0, grid_cap = 0;  // launch schedule (set by the autotuner)
+    float tune_ms[kTuneVariants] = {};
 };
 // The problems of one lane layout of the L-BFGS kernel: their samples are a
 // contiguous global range [g0, g0 + n).
@@ -180,6 +189,8 @@ extern "C" const char *chisao_last_error(void) { return g_err.c_str(); }
 // ---------------------------------------------------------------------------
 // Creation
 // ---------------------------------------------------------------------------
+static int autotune(chisao_ctx *h);
+
 extern "C" int chisao_init_batched(chisao_handle *out, int n_problems, const chisao_problem *ps,
                                    const chisao_config *cs, const float *const *x0_dev, void *hip_stream) {
     if (!out) return fail(CHISAO_E_INVAL, "null output handle");
@@ -448,6 +459,7 @@ extern "C" int chisao_init_batched(chisao_handle *out, int n_problems, const chi
             }
         }
         HIP_GO(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+        if (!(h->flags & CHISAO_FLAG_NO_AUTOTUNE) && (rc = autotune(h))) goto fail_out;
     }
 #undef ALLOC
 #undef HIP_GO
@@ -505,8 +517,57 @@ static long tile_bound(chisao_ctx *h, const EvalClass &c, int vc_kind, bool fd) 
 
 static hipError_t run_eval(chisao_ctx *h, const EvalClass &c, EvalArgs &a, int center, bool fd, bool grad) {
     a.max_tiles = tile_bound(h, c, a.vc_kind, fd);
+    a.order = c.order;
+    a.grid_cap = c.grid_cap;
     const int cls = fd ? CHISAO_PROF_EVAL_FD : center;
     return timed(h, cls, [&] { return launch_eval(a, c.DP, c.family, center, fd, grad, h->cur); });
+}
+
+// Autotuner: per evaluation class, time each launch schedule on a value +
+// gradient pass over every sample of the class's problems (the starting
+// population; F and G are recomputed by the first cycle) and keep the
+// fastest.  Every schedule computes the same tiles, so results do not depend
+// on the choice.
+static int autotune(chisao_ctx *h) {
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    int rc = CHISAO_OK;
+    for (EvalClass &c : h->eclasses) {
+        const bool adj = c.grad_mode == CHISAO_GRAD_ADJOINT;
+        float best = 0.0f;
+        int best_v = 0;
+        for (int v = 0; v < kTuneVariants && rc == CHISAO_OK; ++v) {
+            EvalArgs a = base_args(h, c);
+            a.vc_kind = kVcOne;
+            a.F_out = h->D.F;
+            a.G_out = adj ? h->D.G : nullptr;
+            a.max_tiles = tile_bound(h, c, kVcOne, false);
+            a.order = kTuneOrder[v];
+            a.grid_cap = kTuneCap[v];
+            hipError_t e = launch_eval(a, c.DP, c.family, kDirect, false, adj, h->stream);  // warm-up
+            if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
+            for (int r = 0; r < 2 && e == hipSuccess; ++r) e = launch_eval(a, c.DP, c.family, kDirect, false, adj, h->stream);
+            if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) {
+                rc = fail(CHISAO_E_DEVICE, "autotuning launch failed: %s", hipGetErrorString(e));
+                break;
+            }
+            c.tune_ms[v] = ms / 2.0f;
+            if (v == 0 || c.tune_ms[v] < best) {
+                best = c.tune_ms[v];
+                best_v = v;
+            }
+        }
+        c.order = kTuneOrder[best_v];
+        c.grid_cap = kTuneCap[best_v];
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
 }
 
 // value and gradient of the samples on a list: adjoint in one pass; with
@@ -919,6 +980,26 @@ extern "C" int chisao_eval(chisao_handle h, int problem, const float *X_dev, int
         a.G_out = G_dev;
         a.max_tiles = Vfd <= 32 ? (B + (32 / Vfd) - 1) / (32 / Vfd) : (long)B * ((Vfd + 31) / 32);
         HIP_TRY(launch_eval(a, q.DP, q.family, kDirect, true, false, st));
+    }
+    return CHISAO_OK;
+}
+
+extern "C" int chisao_tuning(chisao_handle h, chisao_tuning_entry *out, int cap, int *n_out) {
+    if (!h || !n_out) return fail(CHISAO_E_INVAL, "null argument");
+    const int n = (int)h->eclasses.size();
+    *n_out = n;
+    if (cap < n) return fail(CHISAO_E_RANGE, "capacity %d < %d classes", cap, n);
+    if (!out) return fail(CHISAO_E_INVAL, "null output");
+    for (int i = 0; i < n; ++i) {
+        const EvalClass &c = h->eclasses[i];
+        chisao_tuning_entry &o = out[i];
+        o.padded_d = c.DP;
+        o.family = c.family;
+        o.grad_mode = c.grad_mode;
+        o.n_problems = (int)c.pids.size();
+        o.order = c.order;
+        o.grid_cap = c.grid_cap > 0 ? c.grid_cap : 8192;
+        for (int v = 0; v < CHISAO_TUNE_VARIANTS; ++v) o.ms[v] = v < kTuneVariants ? c.tune_ms[v] : 0.0f;
     }
     return CHISAO_OK;
 }

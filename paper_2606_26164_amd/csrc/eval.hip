@@ -137,7 +137,22 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void
     __syncthreads();
     const int n_tiles = s_pref[a.n_cls];
 
-    for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+    // Tile order.  Linear: block b takes tiles b, b + G, ...  XCD-chunked:
+    // workgroups are dispatched round-robin over the 8 XCDs, so block b runs on
+    // XCD b % 8; that XCD's blocks take a contiguous eighth of the tile range,
+    // which in class order spans fewer problems, so each XCD's L2 holds the
+    // precision matrices of fewer problems.
+    int t0 = 0, first = blockIdx.x, stride = gridDim.x, span = n_tiles;
+    if (a.order == 1) {
+        constexpr int kXcd = 8;
+        span = (n_tiles + kXcd - 1) / kXcd;
+        t0 = (blockIdx.x % kXcd) * span;
+        first = blockIdx.x / kXcd;
+        stride = gridDim.x / kXcd;
+    }
+    for (int it = first; it < span; it += stride) {
+        const int tile = t0 + it;
+        if (tile >= n_tiles) break;
         // ---- the tile's problem ---------------------------------------------
         int lo_j = 0, hi_j = a.n_cls - 1;
         while (lo_j < hi_j) {
@@ -495,8 +510,10 @@ static hipError_t dispatch_modes(const EvalArgs &a, int center, bool fd, bool gr
 hipError_t launch_eval(const EvalArgs &a, int DP, int family, int center, bool fd, bool grad, hipStream_t st) {
     if (a.max_tiles <= 0 || a.n_cls <= 0) return hipSuccess;
     if (a.n_cls > kMaxClass) return hipErrorInvalidValue;
-    const long cap = 8192;
-    const dim3 grid((unsigned)(a.max_tiles < cap ? a.max_tiles : cap));
+    const long cap = a.grid_cap > 0 ? a.grid_cap : 8192;
+    long g = a.max_tiles < cap ? a.max_tiles : cap;
+    if (a.order == 1) g = (g + 7) / 8 * 8;  // whole rounds over the XCDs
+    const dim3 grid((unsigned)g);
     switch (DP) {
         case 16: return family ? dispatch_modes<16, 1>(a, center, fd, grad, grid, st)
                                : dispatch_modes<16, 0>(a, center, fd, grad, grid, st);

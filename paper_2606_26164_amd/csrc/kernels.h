@@ -33,6 +33,8 @@ struct EvalArgs {
     int trial_next;       // trial centres: list receiving rejected samples (-1: mark failed)
     int need_bit;         // phase_mask bit a problem must have set to take part (0: none)
     int step_limit;       // 1: only problems with step < n_cloud, 2: step < n_anti, 0: all
+    int order;            // tile order: 0 linear, 1 XCD-chunked (block b runs on XCD b % 8)
+    int grid_cap;         // most workgroups launched (0: 8192); a multiple of 8 with order 1
     int nz_kind;          // evaluation noise of noisy problems: -1 none, 0 one draw per value, 1 gate mean
     uint32_t nz_base;     // noise sub-stream base (kind 0); the noise step is `step`
 };

@@ -130,3 +130,30 @@ def test_batch_validation():
         # a batch keeps one cycle count: setting another k on one problem is refused
         st.k = 1
         assert opt.lib.chisao_set_state(opt.h, 0, C.byref(st)) == L.E_INVAL
+
+
+def test_autotuned_schedule_changes_timing_only():
+    from paper_2606_26164_amd import _lib as L
+    from paper_2606_26164_amd.api import Optimizer
+
+    items = _mixed_batch(n_osc=3)
+    out = []
+    for flags in (0, L.FLAG_NO_AUTOTUNE):
+        with Optimizer.batched(items, flags=flags) as opt:
+            tun = opt.tuning()
+            opt.cycle(3)
+            out.append(([_state(opt, p) for p in range(len(items))], tun))
+    tuned, fixed = out[0][1], out[1][1]
+    print("\n" + "\n".join(str(t) for t in tuned))
+    # classes: (padded d, family, gradient mode) of the five problems
+    assert sorted((t["padded_d"], t["family"], t["grad_mode"]) for t in tuned) == \
+        [(16, 0, 0), (16, 0, 1), (16, 1, 1), (64, 0, 1)]
+    assert sum(t["n_problems"] for t in tuned) == len(items)
+    for t in tuned:
+        assert all(ms > 0 for ms in t["ms"])
+        best = min(range(L.TUNE_VARIANTS), key=lambda v: t["ms"][v])
+        assert (t["order"], t["grid_cap"]) == (best % 2, 8192 if best < 2 else 1024)
+    for t in fixed:
+        assert (t["order"], t["grid_cap"]) == (0, 8192) and all(ms == 0 for ms in t["ms"])
+    for p in range(len(items)):
+        _assert_same(out[0][0][p], out[1][0][p], f"problem {p}: tuned vs default schedule")
