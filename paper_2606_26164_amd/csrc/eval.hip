@@ -56,7 +56,7 @@ __device__ __forceinline__ void load_frag(const gfloat *p, float out[MB]) {
 template <int KS, int MB>
 struct CompRegs {
     float pa[KS][MB];
-    float muB[KS], muC[KS];
+    float muB[KS];
     float lc2;
 };
 
@@ -93,7 +93,7 @@ __device__ __forceinline__ long tiles_of(int count, int V, int &jpw, int &wpj) {
 }
 
 template <int DP, int FAM, bool GRAD, int CENTER, bool FD>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void eval_kernel(EvalArgs a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void eval_kernel(EvalArgs a) {
     constexpr int KS = DP / 4;
     constexpr int MB = DP / 16;
     constexpr int LD = DP + 1;  // padded row: conflict-free column reads
@@ -263,36 +263,36 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void
                 for (int i = 0; i < KS; ++i) gacc[nb][i] = 0.0f;
         }
         // ---- stream the components -----------------------------------------
-        // Component k+1's operands are loaded into a second register set while
-        // component k is contracted (the loop is unrolled by two so the sets
-        // alternate without copies).  The loads go through global-address-space
-        // pointers: flat loads would also count against the LDS counter, and
-        // the cross-lane shuffles of the epilogue would then wait for them.
+        // Two waves per SIMD: while one waits for a component's operands or
+        // works through the log-sum-exp epilogue on the VALU, the other keeps
+        // the matrix core busy; a wave raises its priority for the duration of
+        // its MFMA block so the arbiter keeps the matrix core fed.  Operands
+        // come through global-address-space pointers: flat loads would also
+        // count against the LDS counter, and the cross-lane reductions of the
+        // epilogue would then wait for them.
         const gfloat *Pfrag = as_global(pd.Pfrag), *muBk = as_global(pd.muB), *muCk = as_global(pd.muC),
                      *logc2 = as_global(pd.logc2);
         const float nu = pd.nu, nupd = pd.nu_plus_d;
-        CompRegs<KS, MB> ra, rb;
+        CompRegs<KS, MB> ra;
         auto load = [&](int k, CompRegs<KS, MB> &r) {
             const gfloat *pf = Pfrag + (size_t)k * KS * kWave * MB + lane * MB;
             const gfloat *mb_p = muBk + ((size_t)k * 4 + g) * KS;
-            const gfloat *mc_p = muCk + ((size_t)k * 4 + g) * KS;
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks) load_frag<MB>(pf + (size_t)ks * kWave * MB, r.pa[ks]);
 #pragma unroll
             for (int i = 0; i < KS; i += 4) {
                 const f32x4 vb = *reinterpret_cast<const gf32x4 *>(mb_p + i);
-                const f32x4 vc = *reinterpret_cast<const gf32x4 *>(mc_p + i);
                 r.muB[i] = vb[0]; r.muB[i + 1] = vb[1]; r.muB[i + 2] = vb[2]; r.muB[i + 3] = vb[3];
-                r.muC[i] = vc[0]; r.muC[i + 1] = vc[1]; r.muC[i + 2] = vc[2]; r.muC[i + 3] = vc[3];
             }
             r.lc2 = logc2[k];
         };
-        auto step = [&](const CompRegs<KS, MB> &r) {
+        auto step = [&](int k, const CompRegs<KS, MB> &r) {
             f32x4 acc[NB][MB];
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
                 for (int mb = 0; mb < MB; ++mb) acc[nb][mb] = f32x4{0.f, 0.f, 0.f, 0.f};
+            __builtin_amdgcn_s_setprio(1);
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks) {
 #pragma unroll
@@ -303,6 +303,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void
                         acc[nb][mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(r.pa[ks][mb], b, acc[nb][mb], 0, 0, 0);
                 }
             }
+            __builtin_amdgcn_s_setprio(0);
+            // centre coordinates in accumulator-lane order, only needed now
+            float muC[KS];
+            const gfloat *mc_p = muCk + ((size_t)k * 4 + g) * KS;
+#pragma unroll
+            for (int i = 0; i < KS; i += 4) {
+                const f32x4 vc = *reinterpret_cast<const gf32x4 *>(mc_p + i);
+                muC[i] = vc[0]; muC[i + 1] = vc[1]; muC[i + 2] = vc[2]; muC[i + 3] = vc[3];
+            }
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) {
                 float q = 0.0f;
@@ -310,7 +319,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void
                 for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
                     for (int rr = 0; rr < 4; ++rr)
-                        q = fmaf(xC[nb][mb * 4 + rr] - r.muC[mb * 4 + rr], acc[nb][mb][rr], q);
+                        q = fmaf(xC[nb][mb * 4 + rr] - muC[mb * 4 + rr], acc[nb][mb][rr], q);
                 q = rows4_sum(q);
                 float l2, w = 1.0f;
                 if constexpr (FAM == 0) {
@@ -340,15 +349,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void
             }
         };
         const int K = pd.K;
-        // (the prefetch past the last component reloads it: no branch, so the
-        // wait before each step covers only the set it uses)
-        load(0, ra);
-        for (int k = 0; k < K; k += 2) {
-            load(min(k + 1, K - 1), rb);
-            step(ra);
-            if (k + 1 >= K) break;
-            load(min(k + 2, K - 1), ra);
-            step(rb);
+        for (int k = 0; k < K; ++k) {
+            load(k, ra);
+            step(k, ra);
         }
         // ---- results to LDS ------------------------------------------------
         // Noisy problems: every value the method sees carries sigma_n z, z the
