@@ -60,7 +60,8 @@ struct CompRegs {
     float lc2;
 };
 
-constexpr int kMaxClass = 256;  // problems per class (LDS budget: 2 waves per SIMD)
+constexpr int kMaxClass = 256;
+constexpr int kTrialSplit = 4;  // waves per line-search tile  // problems per class (LDS budget: 2 waves per SIMD)
 
 __device__ __forceinline__ int job_count(const EvalArgs &a, int p, const ProblemDesc &pd) {
     if (a.ext_n >= 0) return a.ext_n;
@@ -92,11 +93,19 @@ __device__ __forceinline__ long tiles_of(int count, int V, int &jpw, int &wpj) {
     return (long)count * wpj;
 }
 
-template <int DP, int FAM, bool GRAD, int CENTER, bool FD>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void eval_kernel(EvalArgs a) {
+// SPLIT waves share a tile: each contracts a contiguous part of the
+// components and the first (lead) wave merges the partial log-sum-exp states
+// in wave order, then runs the epilogue.  Line-search launches are small (a
+// few thousand points), so their time is the latency of one tile's pass over
+// all K components; splitting the components cuts that latency.
+template <int DP, int FAM, bool GRAD, int CENTER, bool FD, int SPLIT>
+__global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2))) void eval_kernel(EvalArgs a) {
     constexpr int KS = DP / 4;
     constexpr int MB = DP / 16;
     constexpr int LD = DP + 1;  // padded row: conflict-free column reads
+    constexpr int NP = SPLIT > 1 ? SPLIT - 1 : 1;
+    __shared__ float s_pm[NP][NB][kWave], s_ps[NP][NB][kWave];       // partial max / sum of waves 1..
+    __shared__ float s_pg[(SPLIT > 1 && GRAD) ? NP * NB * KS : 1][kWave];  // partial gradient sums
     __shared__ float s_pts[PPW * LD];
     __shared__ float s_g[GRAD ? PPW * LD : 1];
     __shared__ float s_f[PPW];
@@ -109,11 +118,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ev
     __shared__ int s_pref[kMaxClass + 1];
 
     const Dev &D = a.D;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+    const bool lead = SPLIT == 1 || wv == 0;
     const int g = lane >> 4, n = lane & 15;
     const bool ext = a.ext_n >= 0;
     // tile prefix over the problems of the class
-    if (lane == 0) {
+    if (threadIdx.x == 0) {
         int acc = 0;
         unsigned long long pts = 0;
         s_pref[0] = 0;
@@ -176,7 +186,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ev
         const int xs = a.x_stride;
         const int *lst = (!ext && a.list_id >= 0) ? list_ptr(D, a.list_id, pd.s0) : nullptr;
         // ---- point metadata ------------------------------------------------
-        if (lane < PPW) {
+        if (lead && lane < PPW) {
             const int pt = lane;
             int job, v;
             bool valid;
@@ -196,7 +206,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ev
         }
         __syncthreads();
         // ---- generate the points (zero padded to DP) -----------------------
-        for (int e = lane; e < PPW * KS; e += kWave) {
+        for (int e = lead ? lane : PPW * KS; e < PPW * KS; e += kWave) {
             const int pt = e / KS, blk = e % KS, c0 = 4 * blk;
             const int s = s_s[pt];
             float x[4] = {0.f, 0.f, 0.f, 0.f};
@@ -349,9 +359,43 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ev
             }
         };
         const int K = pd.K;
-        for (int k = 0; k < K; ++k) {
+        const int kb = SPLIT == 1 ? 0 : (wv * K) / SPLIT, ke = SPLIT == 1 ? K : ((wv + 1) * K) / SPLIT;
+        for (int k = kb; k < ke; ++k) {
             load(k, ra);
             step(k, ra);
+        }
+        if constexpr (SPLIT > 1) {
+            // merge: m = max(m0, m_v), s = s0 2^(m0-m) + s_v 2^(m_v-m), the
+            // gradient sums alike, for v = 1, 2, ... in order
+            if (!lead) {
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) {
+                    s_pm[wv - 1][nb][lane] = mrun[nb];
+                    s_ps[wv - 1][nb][lane] = srun[nb];
+                    if constexpr (GRAD)
+#pragma unroll
+                        for (int i = 0; i < KS; ++i) s_pg[((wv - 1) * NB + nb) * KS + i][lane] = gacc[nb][i];
+                }
+            }
+            __syncthreads();
+            if (lead) {
+                for (int v = 0; v < SPLIT - 1; ++v) {
+#pragma unroll
+                    for (int nb = 0; nb < NB; ++nb) {
+                        const float mv = s_pm[v][nb][lane];
+                        if (!(mv > -INFINITY)) continue;  // no components in that part
+                        const float mn = fmaxf(mrun[nb], mv);
+                        const float a0 = __builtin_amdgcn_exp2f(mrun[nb] - mn);
+                        const float a1 = __builtin_amdgcn_exp2f(mv - mn);
+                        srun[nb] = fmaf(srun[nb], a0, s_ps[v][nb][lane] * a1);
+                        if constexpr (GRAD)
+#pragma unroll
+                            for (int i = 0; i < KS; ++i)
+                                gacc[nb][i] = fmaf(gacc[nb][i], a0, s_pg[(v * NB + nb) * KS + i][lane] * a1);
+                        mrun[nb] = mn;
+                    }
+                }
+            }
         }
         // ---- results to LDS ------------------------------------------------
         // Noisy problems: every value the method sees carries sigma_n z, z the
@@ -361,6 +405,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ev
         const bool noisy = !ext && a.nz_kind >= 0 && pd.noise_sigma > 0.0f;
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
+            if (!lead) break;
             const int pt = nb * 16 + n;
             float f = (mrun[nb] + __log2f(srun[nb])) * kLn2;
             if (noisy && g == 0 && s_s[pt] >= 0) {
@@ -397,16 +442,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ev
         // ---- epilogues -----------------------------------------------------
         const int os = a.out_stride;
         if constexpr (CENTER == kDirect && !FD) {
-            if (lane < PPW && s_s[lane] >= 0 && a.F_out) a.F_out[s_s[lane]] = s_f[lane];
+            if (lead && lane < PPW && s_s[lane] >= 0 && a.F_out) a.F_out[s_s[lane]] = s_f[lane];
             if constexpr (GRAD) {
-                if (a.G_out)
+                if (lead && a.G_out)
                     for (int e = lane; e < PPW * d; e += kWave) {
                         const int pt = e / d, c = e % d, s = s_s[pt];
                         if (s >= 0) a.G_out[(size_t)s * os + c] = s_g[pt * LD + c];
                     }
             }
         } else if constexpr (FD) {
-            if (lane < PPW) {
+            if (lead && lane < PPW) {
                 const int pt = lane, s = s_s[pt], st = s_st[pt];
                 if (s >= 0 && (st & 1) == 0) {
                     const float gv = (s_f[pt] - s_f[pt + 1]) / s_den[pt];
@@ -418,7 +463,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ev
         } else if constexpr (CENTER == kProbe) {
             // mean over the job's probes, summed in probe order
             const float invM = 1.0f / (float)Vc;
-            for (int e = lane; e < jpw * d; e += kWave) {
+            for (int e = lead ? lane : jpw * d; e < jpw * d; e += kWave) {
                 const int j = e / d, c = e % d, p0 = j * Vc, s = s_s[p0];
                 if (s >= 0) {
                     float acc = 0.0f;
@@ -429,7 +474,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ev
         } else if constexpr (CENTER == kTrial) {
             // Armijo margins f_tr - f - c1 g.(x_tr - x), two lanes per point
             const int DS = D.DS;
-            {
+            if (lead) {
                 const int pt = lane >> 1, h = lane & 1, s = s_s[pt];
                 float dot = 0.0f;
                 if (s >= 0)
@@ -442,7 +487,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ev
                     s_pass[pt] = (s >= 0) && (s_f[pt] - D.F[s] - pd.ls_c1 * dot + 2.0f * pd.noise_sigma >= 0.0f);
             }
             __syncthreads();
-            if (lane < jpw) {
+            if (lead && lane < jpw) {
                 int r = -1;
                 const int p0 = lane * Vc;
                 if (s_s[p0] >= 0)
@@ -451,7 +496,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ev
                 s_acc[lane] = r;
             }
             __syncthreads();
-            for (int e = lane; e < jpw * d; e += kWave) {
+            for (int e = lead ? lane : jpw * d; e < jpw * d; e += kWave) {
                 const int j = e / d, c = e % d, p0 = j * Vc, s = s_s[p0];
                 if (s >= 0 && s_acc[j] >= 0) {
                     const int pa = p0 + s_acc[j];
@@ -465,7 +510,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ev
             // verdict per list position for the compaction that follows:
             // 1 try the remaining trials, 2 accepted (the finite-difference
             // gradient is still due), 3 the search failed, 0 nothing to do
-            if (lane < jpw) {
+            if (lead && lane < jpw) {
                 const int p0 = lane * Vc, sl = s_s[p0];
                 if (sl >= 0) {
                     const int r = s_acc[lane];
@@ -494,19 +539,22 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ev
 template <int DP, int FAM>
 static hipError_t dispatch_modes(const EvalArgs &a, int center, bool fd, bool grad, dim3 grid, hipStream_t st) {
     const dim3 block(kWave);
-#define CHISAO_GO(C, G, F) hipLaunchKernelGGL((eval_kernel<DP, FAM, G, C, F>), grid, block, 0, st, a)
+#define CHISAO_GO(C, G, F) hipLaunchKernelGGL((eval_kernel<DP, FAM, G, C, F, 1>), grid, block, 0, st, a)
+#define CHISAO_GO_SPLIT(C, G, F) \
+    hipLaunchKernelGGL((eval_kernel<DP, FAM, G, C, F, kTrialSplit>), grid, dim3(kWave * kTrialSplit), 0, st, a)
     if (center == kDirect) {
         if (fd) CHISAO_GO(kDirect, false, true);
         else if (grad) CHISAO_GO(kDirect, true, false);
         else CHISAO_GO(kDirect, false, false);
     } else if (center == kTrial) {
-        if (grad) CHISAO_GO(kTrial, true, false);
-        else CHISAO_GO(kTrial, false, false);
+        if (grad) CHISAO_GO_SPLIT(kTrial, true, false);
+        else CHISAO_GO_SPLIT(kTrial, false, false);
     } else {
         if (fd) CHISAO_GO(kProbe, false, true);
         else CHISAO_GO(kProbe, true, false);
     }
 #undef CHISAO_GO
+#undef CHISAO_GO_SPLIT
     return hipGetLastError();
 }
 
