@@ -38,7 +38,15 @@ def lbfgs_bytes_per_step(d: int, m: int) -> int:
     """Algorithmic HBM bytes of one L-BFGS direction + pair update for one
     sample with a full history: read x, x_prev, g, g_prev, S, Y (m d each), rho;
     write the new pair and the direction."""
-    return 4 * (4 * d + 2 * m * d + m + 2 * d + 1 + d)
+    return lbfgs_bytes(d, 1, m)
+
+
+def lbfgs_bytes(d: int, steps: int, pairs: int) -> int:
+    """Algorithmic HBM bytes of `steps` L-BFGS sample-steps whose two-loops read
+    `pairs` history pairs in total: per step x, x_prev, g, g_prev read (4d), the
+    new pair written (2d + 1) and the direction written (d); per pair s, y and
+    rho read (2d + 1)."""
+    return 4 * (steps * (7 * d + 1) + pairs * (2 * d + 1))
 
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -180,12 +188,15 @@ def main(argv=None):
     lb = prof.get("lbfgs")
     roof_lbfgs = None
     if lb and lb["ms"] > 0:
-        bps = lbfgs_bytes_per_step(prob.d, cfg.m)
-        gbs = lb["points"] * bps / (lb["ms"] * 1e-3) / 1e9
+        pairs = prof.get("lbfgs_pairs", {}).get("points", 0)
+        nbytes = lbfgs_bytes(prob.d, lb["points"], pairs)
+        gbs = nbytes / (lb["ms"] * 1e-3) / 1e9
         roof_lbfgs = dict(bound="hbm", achieved=gbs, peak=PEAK_HBM_GBS, unit="GB/s", frac=gbs / PEAK_HBM_GBS,
-                          traffic=None, kernel="lbfgs_step_kernel", bytes_per_sample_step=bps,
+                          traffic=None, kernel="lbfgs_step_kernel", bytes_per_launch=nbytes / max(lb["launches"], 1),
+                          sample_steps=lb["points"], history_pairs_read=pairs,
+                          bytes_per_sample_step_full_history=lbfgs_bytes_per_step(prob.d, cfg.m),
                           launches=lb["launches"], avg_launch_ms=lb["ms"] / max(lb["launches"], 1))
-    kernel_ms = {k: round(v["ms"] / args.steps, 3) for k, v in prof.items()}
+    kernel_ms = {k: round(v["ms"] / args.steps, 3) for k, v in prof.items() if v["launches"]}
 
     cpu = None
     if args.cpu_samples > 0:

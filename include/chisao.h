@@ -150,7 +150,8 @@ typedef struct {
 #define CHISAO_PROF_EVAL_TRIAL 1  /* line-search trial points */
 #define CHISAO_PROF_EVAL_PROBE 2  /* Hands Like Clouds smoothing probes */
 #define CHISAO_PROF_EVAL_FD 3     /* central-difference stencil points */
-#define CHISAO_PROF_LBFGS 4       /* two-loop directions and curvature pairs */
+#define CHISAO_PROF_LBFGS 4       /* two-loop directions and curvature pairs; points = samples given a direction */
+#define CHISAO_PROF_LBFGS_PAIRS 5 /* points only: history pairs those two-loops read (no launches of its own) */
 #define CHISAO_PROF_CLASSES 8
 typedef struct {
     int32_t launches;

@@ -57,7 +57,7 @@ class KernelProfile(C.Structure):
 
 
 PROF_CLASSES = 8
-PROF_NAMES = ("eval_direct", "eval_trial", "eval_probe", "eval_fd", "lbfgs", "unused5", "unused6", "unused7")
+PROF_NAMES = ("eval_direct", "eval_trial", "eval_probe", "eval_fd", "lbfgs", "lbfgs_pairs", "unused6", "unused7")
 
 EXPORTS = ("chisao_init", "chisao_init_batched", "chisao_profile", "chisao_cycle", "chisao_modes", "chisao_get_state", "chisao_set_state",
            "chisao_run_phases", "chisao_eval", "chisao_destroy", "chisao_last_error", "chisao_tuning")

@@ -65,6 +65,7 @@ int pad_dim(int d) { return d <= 16 ? 16 : (d <= 32 ? 32 : 64); }
 // (linear, XCD-chunked) x grid (8192 workgroups, dispatched as slots free up;
 // 1024, one resident wave per SIMD looping over tiles).
 constexpr int kTuneVariants = 4;
+constexpr int kMaxTrials = 16;  // upper bound of ls_max
 constexpr int kTuneOrder[kTuneVariants] = {0, 1, 0, 1};
 constexpr int kTuneCap[kTuneVariants] = {8192, 8192, 1024, 1024};
 int coords_per_lane(int d) { return d <= 16 ? 1 : (d <= 32 ? 2 : 4); }
@@ -503,11 +504,12 @@ static EvalArgs base_args(chisao_ctx *h, const EvalClass &c) {
 }
 
 // Upper bound on the tiles of a launch (sizes its grid).
-static long tile_bound(chisao_ctx *h, const EvalClass &c, int vc_kind, bool fd) {
+static long tile_bound(chisao_ctx *h, const EvalClass &c, int vc_kind, bool fd, int trial_lo = 0, int trial_cnt = 0) {
     long t = 0;
     for (int p : c.pids) {
         const ProblemDesc &q = h->pdh[p];
-        const int Vc = vc_kind == kVcTrialRest ? q.ls_max - 1 : (vc_kind == kVcProbes ? q.M : 1);
+        const int Vc = vc_kind == kVcTrialRest ? std::max(0, std::min(trial_cnt, q.ls_max - trial_lo))
+                                               : (vc_kind == kVcProbes ? q.M : 1);
         const long V = (long)Vc * (fd ? 2 * q.d : 1);
         if (V <= 0) continue;
         t += V <= 32 ? (q.N + (32 / V) - 1) / (32 / V) : (long)q.N * ((V + 31) / 32);
@@ -516,7 +518,7 @@ static long tile_bound(chisao_ctx *h, const EvalClass &c, int vc_kind, bool fd) 
 }
 
 static hipError_t run_eval(chisao_ctx *h, const EvalClass &c, EvalArgs &a, int center, bool fd, bool grad) {
-    a.max_tiles = tile_bound(h, c, a.vc_kind, fd);
+    a.max_tiles = tile_bound(h, c, a.vc_kind, fd, a.trial_lo, a.trial_cnt);
     a.order = c.order;
     a.grid_cap = c.grid_cap;
     const int cls = fd ? CHISAO_PROF_EVAL_FD : center;
@@ -615,16 +617,17 @@ static hipError_t phase_converge(chisao_ctx *h) {
         // the steppers of iteration t go to list_out; t+1 reads them back
         const int list_in = t == 1 ? L_ACT : ((t - 1) % 2 ? L_T1 : L_T1B);
         const int list_out = t % 2 ? L_T1 : L_T1B;
-        if ((e = launch_reset_counts(D, (1 << list_out) | (1 << L_T2) | (1 << L_FD), st)) != hipSuccess) return e;
+        if ((e = launch_reset_counts(D, (1 << list_out) | (1 << L_T2) | (1 << L_T3) | (1 << L_FD), st)) != hipSuccess)
+            return e;
         for (const LbfgsClass &lc : h->lclasses)
             if ((e = timed(h, CHISAO_PROF_LBFGS,
                            [&] { return launch_lbfgs_step(D, t, lc.cpl, list_in, lc.g0, lc.n, st); })) != hipSuccess)
                 return e;
         if (t > D.n_conv_max) break;
-        if ((e = launch_compact(D, list_in, list_out, -1, false, D.prof + CHISAO_PROF_LBFGS, st)) != hipSuccess)
+        if ((e = launch_compact(D, list_in, list_out, -1, false, D.prof + CHISAO_PROF_LBFGS, st,
+                                D.prof + CHISAO_PROF_LBFGS_PAIRS)) != hipSuccess)
             return e;
-        // first trial t = 1 for every stepper; the rest (speculative, all at
-        // once) for those whose first trial failed
+        // first trial t = 1 for every stepper
         for (const EvalClass &c : h->eclasses) {
             EvalArgs a = base_args(h, c);
             a.list_id = list_out;
@@ -635,16 +638,26 @@ static hipError_t phase_converge(chisao_ctx *h) {
             if ((e = run_eval(h, c, a, kTrial, false, c.grad_mode == CHISAO_GRAD_ADJOINT)) != hipSuccess) return e;
         }
         if ((e = launch_compact(D, list_out, L_T2, L_FD, true, nullptr, st)) != hipSuccess) return e;
-        for (const EvalClass &c : h->eclasses) {
-            EvalArgs a = base_args(h, c);
-            a.list_id = L_T2;
-            a.vc_kind = kVcTrialRest;
-            a.trial_next = -1;
-            a.step = t;
-            a.nz_kind = 0;
-            if ((e = run_eval(h, c, a, kTrial, false, c.grad_mode == CHISAO_GRAD_ADJOINT)) != hipSuccess) return e;
+        // the remaining trials in two stages: t = 1/2, 1/4, then the rest only
+        // for searches that rejected those too.  Most searches that reject
+        // t = 1 accept one of the next two, so evaluating every remaining
+        // trial at once would mostly compute points that are never used.
+        for (int stage = 0; stage < 2; ++stage) {
+            const int lst = stage ? L_T3 : L_T2;
+            for (const EvalClass &c : h->eclasses) {
+                EvalArgs a = base_args(h, c);
+                a.list_id = lst;
+                a.vc_kind = kVcTrialRest;
+                a.trial_lo = stage ? 3 : 1;
+                a.trial_cnt = stage ? kMaxTrials : 2;
+                a.trial_next = stage ? -1 : L_T3;
+                a.step = t;
+                a.nz_kind = 0;
+                if ((e = run_eval(h, c, a, kTrial, false, c.grad_mode == CHISAO_GRAD_ADJOINT)) != hipSuccess)
+                    return e;
+            }
+            if ((e = launch_compact(D, lst, stage ? -1 : L_T3, L_FD, true, nullptr, st)) != hipSuccess) return e;
         }
-        if ((e = launch_compact(D, L_T2, -1, L_FD, true, nullptr, st)) != hipSuccess) return e;
         for (const EvalClass &c : h->eclasses) {
             if (c.grad_mode == CHISAO_GRAD_ADJOINT) continue;
             EvalArgs b = base_args(h, c);

@@ -147,7 +147,8 @@ struct ProblemDesc {
 // ---------------------------------------------------------------------------
 // L_T1 and L_T1B alternate between L-BFGS iterations: one holds the samples
 // that took a step in the previous iteration, the other collects this one's.
-enum ListId { L_ACT = 0, L_T1, L_T1B, L_T2, L_FD, L_UNF, L_STK, O_SLOTS, O_FREE, O_PEAKS, kNumLists };
+// L_T2 / L_T3: searches still open after the first trial / after trials 1-2.
+enum ListId { L_ACT = 0, L_T1, L_T1B, L_T2, L_T3, L_FD, L_UNF, L_STK, O_SLOTS, O_FREE, O_PEAKS, kNumLists };
 
 struct Ctl {
     int k;  // cycles completed

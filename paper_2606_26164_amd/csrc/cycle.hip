@@ -128,7 +128,7 @@ hipError_t launch_reset_counts(const Dev &D, int mask, hipStream_t st) {
 // one address serialise in the L2, which made per-wave appends the dominant
 // cost of the L-BFGS step.
 __global__ __launch_bounds__(kBlock) void compact_kernel(Dev D, int src, int dst1, int dst2, int count_fail,
-                                                         unsigned long long *tally) {
+                                                         unsigned long long *tally, unsigned long long *tally_pairs) {
     __shared__ int s_pmin;
     __shared__ int s_wc[3][kWavesPerBlock];
     __shared__ int s_base[3];
@@ -181,6 +181,12 @@ __global__ __launch_bounds__(kBlock) void compact_kernel(Dev D, int src, int dst
                     list_ptr(D, dst, D.pd[pl].s0)[off] = s;
                 }
             }
+            // L-BFGS accounting: history pairs the steppers' two-loops used
+            if (tally_pairs) {
+                float cnt = (mine && v == 1) ? (float)D.cnt[s] : 0.0f;
+                cnt = wave_sum(cnt);
+                if (lane == 0 && cnt > 0.0f) atomicAdd(tally_pairs, (unsigned long long)cnt);
+            }
             pending = pending && !mine;
             __syncthreads();
         }
@@ -188,9 +194,9 @@ __global__ __launch_bounds__(kBlock) void compact_kernel(Dev D, int src, int dst
 }
 
 hipError_t launch_compact(const Dev &D, int src, int dst1, int dst2, bool count_fail, unsigned long long *tally,
-                          hipStream_t st) {
+                          hipStream_t st, unsigned long long *tally_pairs) {
     hipLaunchKernelGGL(compact_kernel, dim3(grid_for(D.NT, kBlock, 4096)), dim3(kBlock), 0, st, D, src, dst1, dst2,
-                       (int)count_fail, tally);
+                       (int)count_fail, tally, tally_pairs);
     return hipGetLastError();
 }
 

@@ -72,7 +72,7 @@ __device__ __forceinline__ int job_count(const EvalArgs &a, int p, const Problem
 }
 __device__ __forceinline__ int centres(const EvalArgs &a, const ProblemDesc &pd) {
     switch (a.vc_kind) {
-        case kVcTrialRest: return pd.ls_max - 1;
+        case kVcTrialRest: return max(0, min(a.trial_cnt, pd.ls_max - a.trial_lo));
         case kVcProbes: return pd.M;
         default: return 1;
     }
@@ -176,7 +176,7 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
         const int d = pd.d;
         const int count = job_count(a, p, pd);
         const int Vc = centres(a, pd);
-        const int r0 = a.vc_kind == kVcTrialRest ? 1 : 0;
+        const int r0 = a.vc_kind == kVcTrialRest ? a.trial_lo : 0;
         const int Vs = FD ? 2 * d : 1;
         const int V = Vc * Vs;
         int jpw, wpj;
@@ -519,7 +519,7 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
                         D.F[sl] = s_f[p0 + r];
                         D.status[sl] = (uint8_t)(kStAccept | (r0 + r));
                         verdict = GRAD ? 0 : 2;
-                    } else if (a.trial_next >= 0 && pd.ls_max > 1) {
+                    } else if (a.trial_next >= 0 && r0 + Vc < pd.ls_max) {
                         verdict = 1;
                     } else {
                         D.status[sl] = kStFail;

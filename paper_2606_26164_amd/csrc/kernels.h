@@ -30,7 +30,8 @@ struct EvalArgs {
     float *F_out;         // direct centres: value per job row (may be null)
     float *G_out;         // direct centres: gradient rows (may be null)
     int out_stride;
-    int trial_next;       // trial centres: list receiving rejected samples (-1: mark failed)
+    int trial_next;       // trial centres: -1 when no later stage follows (a search none of whose trials passes fails)
+    int trial_lo, trial_cnt;  // kVcTrialRest: trials trial_lo .. trial_lo + trial_cnt - 1, capped at ls_max
     int need_bit;         // phase_mask bit a problem must have set to take part (0: none)
     int step_limit;       // 1: only problems with step < n_cloud, 2: step < n_anti, 0: all
     int order;            // tile order: 0 linear, 1 XCD-chunked (block b runs on XCD b % 8)
@@ -59,9 +60,10 @@ hipError_t launch_reset_counts(const Dev &D, int mask, hipStream_t st);
 // of src's segment (j < its count) with flag[j] == v is appended to list
 // dst[v - 1] (v = 1, 2; -1: none); positions with flag == 3 are counted into
 // the problem's ls_fail.  Entries keep ascending position order within a
-// block.  The number appended for v = 1 is added to *tally when not null.
+// block.  The number appended for v = 1 is added to *tally when not null, and
+// the history pair counts (D.cnt) of those samples to *tally_pairs.
 hipError_t launch_compact(const Dev &D, int src, int dst1, int dst2, bool count_fail, unsigned long long *tally,
-                          hipStream_t st);
+                          hipStream_t st, unsigned long long *tally_pairs = nullptr);
 hipError_t launch_build_unfrozen(const Dev &D, hipStream_t st);
 // L-BFGS step over the samples listed in `samples` (nullptr: all NT), all of
 // whose problems have d <= 16 * cpl.
