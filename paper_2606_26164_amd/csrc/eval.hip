@@ -61,7 +61,11 @@ struct CompRegs {
 };
 
 constexpr int kMaxClass = 256;
-constexpr int kTrialSplit = 4;  // waves per line-search tile  // problems per class (LDS budget: 2 waves per SIMD)
+// waves per line-search tile: at DP = 64 a tile's pass over the components is
+// long enough to be worth splitting; smaller components are cheap per tile
+// and the merge would only add work
+template <int DP>
+constexpr int trial_split() { return DP == 64 ? 4 : 1; }  // problems per class (LDS budget: 2 waves per SIMD)
 
 __device__ __forceinline__ int job_count(const EvalArgs &a, int p, const ProblemDesc &pd) {
     if (a.ext_n >= 0) return a.ext_n;
@@ -360,9 +364,28 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
         };
         const int K = pd.K;
         const int kb = SPLIT == 1 ? 0 : (wv * K) / SPLIT, ke = SPLIT == 1 ? K : ((wv + 1) * K) / SPLIT;
-        for (int k = kb; k < ke; ++k) {
-            load(k, ra);
-            step(k, ra);
+        if constexpr (DP < 64) {
+            // small components: too little work per component to hide its load
+            // latency behind the other wave, so the next one is loaded into a
+            // second register set while this one is contracted (the set is
+            // small at DP <= 32); the prefetch past the end reloads the last
+            // component, which keeps the loop branch-free
+            if (kb < ke) {
+                CompRegs<KS, MB> rb;
+                load(kb, ra);
+                for (int k = kb; k < ke; k += 2) {
+                    load(min(k + 1, ke - 1), rb);
+                    step(k, ra);
+                    if (k + 1 >= ke) break;
+                    load(min(k + 2, ke - 1), ra);
+                    step(k + 1, rb);
+                }
+            }
+        } else {
+            for (int k = kb; k < ke; ++k) {
+                load(k, ra);
+                step(k, ra);
+            }
         }
         if constexpr (SPLIT > 1) {
             // merge: m = max(m0, m_v), s = s0 2^(m0-m) + s_v 2^(m_v-m), the
@@ -540,8 +563,9 @@ template <int DP, int FAM>
 static hipError_t dispatch_modes(const EvalArgs &a, int center, bool fd, bool grad, dim3 grid, hipStream_t st) {
     const dim3 block(kWave);
 #define CHISAO_GO(C, G, F) hipLaunchKernelGGL((eval_kernel<DP, FAM, G, C, F, 1>), grid, block, 0, st, a)
-#define CHISAO_GO_SPLIT(C, G, F) \
-    hipLaunchKernelGGL((eval_kernel<DP, FAM, G, C, F, kTrialSplit>), grid, dim3(kWave * kTrialSplit), 0, st, a)
+#define CHISAO_GO_SPLIT(C, G, F)                                                                       \
+    hipLaunchKernelGGL((eval_kernel<DP, FAM, G, C, F, trial_split<DP>()>), grid, dim3(kWave * trial_split<DP>()), 0, \
+                       st, a)
     if (center == kDirect) {
         if (fd) CHISAO_GO(kDirect, false, true);
         else if (grad) CHISAO_GO(kDirect, true, false);
