@@ -131,6 +131,7 @@ def main(argv=None):
     ap.add_argument("--fd-steps", type=int, default=1, help="finite-difference cycles timed (0: skip)")
     ap.add_argument("--N", type=int, default=65536)
     ap.add_argument("--cpu-samples", type=int, default=2048, help="oracle baseline sample size (0: skip)")
+    ap.add_argument("--batch-steps", type=int, default=3, help="64-problem batch cycles timed (0: skip)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before the timed cycles, copy a buffer of this size once (a reference kernel of known "
                          "traffic for hardware-counter scaling)")
@@ -198,6 +199,24 @@ def main(argv=None):
                           launches=lb["launches"], avg_launch_ms=lb["ms"] / max(lb["launches"], 1))
     kernel_ms = {k: round(v["ms"] / args.steps, 3) for k, v in prof.items() if v["launches"]}
 
+    batch = None
+    if args.batch_steps > 0:
+        items = W.config4()
+        si = sum(c.N * (c.n_conv + c.n_cloud + c.n_anti) for _, c, _ in items)
+        from paper_2606_26164_amd.api import Optimizer
+
+        with Optimizer.batched(items) as opt:
+            opt.cycle(1)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            opt.cycle(args.batch_steps)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t) / args.batch_steps
+        batch = dict(workload=f"{len(items)} independent problems in one handle (d in 2..64, K in 4..64, "
+                              f"N in 1024..16384, {sum(c.N for _, c, _ in items)} samples), adjoint, graph replay",
+                     ms_per_step=dt * 1e3, value=si / dt, unit="sample-iterations/s", cycles=args.batch_steps)
+        log(f"batch: {dt * 1e3:.1f} ms/cycle, {si / dt:.4g} sample-iterations/s")
+
     cpu = None
     if args.cpu_samples > 0:
         log(f"cpu baseline: oracle on {args.cpu_samples} samples")
@@ -224,6 +243,7 @@ def main(argv=None):
             "parallelism": "single GPU",
         },
         "fd": fd,
+        "batched": batch,
         "adjoint_over_fd": (value / fd["value"]) if fd else None,
         "roofline": roof,
         "roofline_lbfgs": roof_lbfgs,
