@@ -278,6 +278,7 @@ extern "C" int chisao_init_batched(chisao_handle *out, int n_problems, const chi
             }
         }
         h->pdh.resize(P);
+        size_t rk_total = 0;
         for (int p = 0; p < n_problems; ++p) {
             const chisao_problem &pr = ps[p];
             const chisao_config &c = cs[p];
@@ -337,6 +338,12 @@ extern "C" int chisao_init_batched(chisao_handle *out, int n_problems, const chi
             q.phase_mask = c.phase_mask;
             q.noise_sigma = pr.noise_sigma;
             q.gate_reps = c.gate_reps > 0 ? c.gate_reps : c.M;
+            {
+                int n2 = 1;
+                while (n2 < c.N) n2 <<= 1;
+                q.rk0 = (int)rk_total;
+                rk_total += (size_t)n2;
+            }
             h->any_noise |= pr.noise_sigma > 0.0f;
         }
         ProblemDesc *pd_dev;
@@ -415,6 +422,7 @@ extern "C" int chisao_init_batched(chisao_handle *out, int n_problems, const chi
         ALLOC(D.cnt, int, N);
         ALLOC(D.lists, int, N * kNumLists);
         ALLOC(D.flag, uint8_t, N);
+        ALLOC(D.rkey, unsigned long long, rk_total);
         ALLOC(D.ctl, Ctl, P);
         ALLOC(D.records, CycleRecord, P * (size_t)D.n_osc);
         ALLOC(D.part, double, P * (size_t)D.n_part_blocks * 129);

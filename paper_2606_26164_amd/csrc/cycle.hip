@@ -487,52 +487,110 @@ hipError_t launch_stick(const Dev &D, hipStream_t st) {
 // first coordinates are staged through LDS; the full row is compared only
 // when the first coordinates are within eps_dup.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void dedup_kernel(Dev D) {
-    __shared__ float t_x0[kBlock];
-    __shared__ float t_f[kBlock];
+// Deduplication in rank order.  The stuck samples of a problem are sorted by
+// (f descending, index ascending), the strict order of the removal rule; then
+// j is removed iff some sample ranked before it lies within eps_dup.  The
+// decision does not depend on the order in which earlier ranks are checked,
+// so each sample first checks its nearest earlier ranks: converged copies of
+// one mode have nearly equal values and sit next to each other in rank
+// order, so almost every sample is settled there.  The few that are not (the
+// best sample of each cluster, samples of loose clusters) then scan all
+// earlier ranks cooperatively, 256 ranks at a time through LDS.
+constexpr int kRankCap = 8192;  // sorted in LDS up to this many stuck samples, in global memory above
+constexpr int kRankBlock = 1024;
+constexpr int kNearRanks = 8;
+
+__device__ __forceinline__ unsigned long long rank_key(float f, int s) {
+    const uint32_t b = __float_as_uint(f);
+    const uint32_t up = (b & 0x80000000u) ? ~b : (b | 0x80000000u);  // ascending with f
+    return ((unsigned long long)(~up) << 32) | (uint32_t)s;            // f descending, then index
+}
+
+// Bitonic sort (ascending) of key[0, n2), n2 a power of two, by one workgroup.
+__device__ void bitonic_sort(unsigned long long *key, int n2) {
+    for (int k = 2; k <= n2; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int t = threadIdx.x; t < n2; t += blockDim.x) {
+                const int u = t ^ j;
+                if (u > t) {
+                    const unsigned long long a = key[t], b = key[u];
+                    if ((a > b) == ((t & k) == 0)) {
+                        key[t] = b;
+                        key[u] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+__global__ __launch_bounds__(kRankBlock) void dedup_rank_kernel(Dev D) {
+    __shared__ unsigned long long lkey[kRankCap];
+    const int p = blockIdx.x;
+    const ProblemDesc &pd = D.pd[p];
+    if (!((pd.phase_mask >> 3) & 1)) return;
+    const int ns = D.ctl[p].count[L_STK];
+    if (ns == 0) return;
+    const int *lst = list_ptr(D, L_STK, pd.s0);
+    const float *Fv = gate_values(D, pd);
+    int n2 = 1;
+    while (n2 < ns) n2 <<= 1;
+    // above kRankCap the keys live in the problem's global scratch (n2 <= its length)
+    unsigned long long *key = ns <= kRankCap ? lkey : D.rkey + pd.rk0;
+    for (int t = threadIdx.x; t < n2; t += blockDim.x) key[t] = t < ns ? rank_key(Fv[lst[t]], lst[t]) : ~0ull;
+    __syncthreads();
+    bitonic_sort(key, n2);
+    int *out = list_ptr(D, L_RANK, pd.s0);
+    for (int t = threadIdx.x; t < ns; t += blockDim.x) out[t] = (int)(key[t] & 0xFFFFFFFFull);
+}
+
+__global__ __launch_bounds__(kBlock) void dedup_scan_kernel(Dev D) {
     __shared__ int t_i[kBlock];
+    __shared__ float t_x0[kBlock];
     const int p = blockIdx.y;
     const ProblemDesc &pd = D.pd[p];
     if (!((pd.phase_mask >> 3) & 1)) return;
     const int ns = D.ctl[p].count[L_STK];
-    const int *lst = list_ptr(D, L_STK, pd.s0);
+    const int *rk = list_ptr(D, L_RANK, pd.s0);
     const int d = pd.d, DS = D.DS;
     const float eps = pd.eps_dup;
-    for (int base = blockIdx.x * kBlock; base < ns; base += gridDim.x * kBlock) {
-        const int jj = base + threadIdx.x;
-        const int j = jj < ns ? lst[jj] : -1;
+    auto near = [&](int i, int j, float xj0) {
+        if (!(fabsf(D.X[(size_t)i * DS] - xj0) < eps)) return false;
+        for (int c = 1; c < d; ++c)
+            if (!(fabsf(D.X[(size_t)i * DS + c] - D.X[(size_t)j * DS + c]) < eps)) return false;
+        return true;
+    };
+    for (int r0 = blockIdx.x * kBlock; r0 < ns; r0 += gridDim.x * kBlock) {
+        const int r = r0 + threadIdx.x;
+        const int j = r < ns ? rk[r] : -1;
         const float xj0 = j >= 0 ? D.X[(size_t)j * DS] : 0.0f;
-        const float *Fv = gate_values(D, pd);
-        const float fj = j >= 0 ? Fv[j] : 0.0f;
         bool rem = false;
-        for (int tb = 0; tb < ns; tb += kBlock) {
-            __syncthreads();
-            const int ii = tb + threadIdx.x;
-            if (ii < ns) {
-                const int i = lst[ii];
-                t_i[threadIdx.x] = i;
-                t_x0[threadIdx.x] = D.X[(size_t)i * DS];
-                t_f[threadIdx.x] = Fv[i];
+        // nearest earlier ranks first
+        for (int q = r - 1; j >= 0 && q >= 0 && q >= r - kNearRanks && !rem; --q) rem = near(rk[q], j, xj0);
+        bool open = j >= 0 && !rem && r > kNearRanks;
+        // the rest cooperatively, over ranks [0, r - kNearRanks)
+        for (int tb = 0; __syncthreads_or(open) && tb < r0 + kBlock; tb += kBlock) {
+            const int q = tb + threadIdx.x;
+            if (q < ns) {
+                t_i[threadIdx.x] = rk[q];
+                t_x0[threadIdx.x] = D.X[(size_t)rk[q] * DS];
             }
             __syncthreads();
-            const int nt = min(kBlock, ns - tb);
-            if (j >= 0 && !rem) {
-                for (int u = 0; u < nt; ++u) {
-                    const int i = t_i[u];
-                    if (i == j || !(fabsf(t_x0[u] - xj0) < eps)) continue;
-                    const float fi = t_f[u];
-                    if (!(fi > fj || (fi == fj && i < j))) continue;
-                    bool near = true;
-                    for (int c = 1; c < d && near; ++c)
-                        near = fabsf(D.X[(size_t)i * DS + c] - D.X[(size_t)j * DS + c]) < eps;
-                    if (near) {
+            if (open) {
+                const int lim = min(kBlock, r - kNearRanks - tb);
+                for (int u = 0; u < lim; ++u) {
+                    if (!(fabsf(t_x0[u] - xj0) < eps)) continue;
+                    if (near(t_i[u], j, xj0)) {
                         rem = true;
                         break;
                     }
                 }
+                if (rem || tb + kBlock >= r - kNearRanks) open = false;
             }
+            __syncthreads();
         }
-        if (j >= 0 && rem) D.removed[j] = 1;
+        if (rem) D.removed[j] = 1;
     }
 }
 
@@ -577,7 +635,8 @@ __global__ void gr_book_kernel(Dev D) {
 hipError_t launch_dedup(const Dev &D, hipStream_t st) {
     hipLaunchKernelGGL(dedup_reset_kernel, dim3(grid_for(D.P, 64)), dim3(64), 0, st, D);
     hipLaunchKernelGGL(clear_removed_kernel, dim3(grid_for(D.NT, kBlock, 1024)), dim3(kBlock), 0, st, D);
-    hipLaunchKernelGGL(dedup_kernel, dim3(grid_for(D.NT / D.P + 1, kBlock, 512), D.P), dim3(kBlock), 0, st, D);
+    hipLaunchKernelGGL(dedup_rank_kernel, dim3(D.P), dim3(kRankBlock), 0, st, D);
+    hipLaunchKernelGGL(dedup_scan_kernel, dim3(grid_for(D.NT / D.P + 1, kBlock, 256), D.P), dim3(kBlock), 0, st, D);
     hipLaunchKernelGGL(dedup_finalize_kernel, dim3(grid_for(D.NT, kBlock, 1024)), dim3(kBlock), 0, st, D);
     hipLaunchKernelGGL(gr_book_kernel, dim3(grid_for(D.P, 64)), dim3(64), 0, st, D);
     return hipGetLastError();
