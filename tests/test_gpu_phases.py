@@ -169,6 +169,30 @@ def test_phases_2_3_stick_and_dedup_parity():
     assert (free.stuck != g3["stuck_pre"]).sum() <= r2.n_borderline
 
 
+@pytest.mark.parametrize("N", [3000, 12000])
+def test_dedup_rank_order_matches_oracle_many_stuck(N):
+    """Deduplication with thousands of stuck samples in a few loose clusters
+    (d=2, wide components): the sorted path in LDS (3000) and in global
+    memory (12000, above the LDS capacity of 8192) against the oracle's
+    all-pairs rule, decisions replayed only where borderline."""
+    prob = W.mixture_problem(7, 2, 5, 3.0, lam_range=(0.5, 1.0))
+    cfg = W.RunConfig(N=N, m=6, n_osc=3, n_conv=30, eps_grad=1e-3, grad_mode=1, seed=4)
+    x0 = W.uniform_population(7, N, prob.lo, prob.hi)
+    with _gpu(prob, cfg, x0) as opt:
+        opt.run_phases(1 << 1)
+        g1 = opt.get_state()
+        opt.run_phases((1 << 2) | (1 << 3))
+        g3 = opt.get_state()
+    n_stuck = int(g3["stuck_pre"].sum())
+    print(f"\nN={N}: stuck {n_stuck}, removed {int(g3['removed'].sum())}, modes {int(g3['stuck'].sum())}")
+    assert n_stuck > 0.6 * N
+    run = _oracle_from(prob, cfg, g1)
+    r2 = run.phase_stick(stuck_in=g3["stuck_pre"], **REPLAY)
+    r3 = run.phase_dedup(removed_in=g3["removed"], **REPLAY)
+    assert r2.n_hard == 0 and r3.n_hard == 0, (r2, r3)
+    np.testing.assert_array_equal(run.stuck, g3["stuck"])
+
+
 def test_phase4_repulse_monkey_parity():
     prob, cfg, x0 = _many_stuck_case()
     with _gpu(prob, cfg, x0) as opt:
