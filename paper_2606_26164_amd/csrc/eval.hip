@@ -60,12 +60,12 @@ struct CompRegs {
     float lc2;
 };
 
-constexpr int kMaxClass = 256;
+constexpr int kMaxClass = 256;  // problems per class (LDS budget: 2 waves per SIMD)
 // waves per line-search tile: at DP = 64 a tile's pass over the components is
 // long enough to be worth splitting; smaller components are cheap per tile
 // and the merge would only add work
 template <int DP>
-constexpr int trial_split() { return DP == 64 ? 4 : 1; }  // problems per class (LDS budget: 2 waves per SIMD)
+constexpr int trial_split() { return DP == 64 ? 4 : 1; }
 
 __device__ __forceinline__ int job_count(const EvalArgs &a, int p, const ProblemDesc &pd) {
     if (a.ext_n >= 0) return a.ext_n;
