@@ -84,7 +84,8 @@ typedef struct {
     int32_t grad_mode;  /* CHISAO_GRAD_FD or CHISAO_GRAD_ADJOINT */
     float fd_h;         /* finite-difference step; auto: h_j = 2^-8 max(1, |x_j|) */
     float ls_c1;        /* Armijo constant of the backtracking line search */
-    int32_t ls_max;     /* backtracking trials t = 1, 1/2, ..., 2^-(ls_max-1); 1..16 */
+    int32_t ls_max;     /* backtracking trials t = 1, 1/2, ..., 2^-(ls_max-1); 1..15 (the decision trace
+                           stores the accepted index in 4 bits, 15 meaning a failed search) */
     float curv_eps;     /* a pair is stored when s'y > curv_eps |s| |y| */
     int32_t gate_reps;  /* noisy problems: the quality gate compares the mean of this many fresh noisy
                            evaluations per sample (0: M); 0..4096 */

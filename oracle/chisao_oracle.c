@@ -566,7 +566,13 @@ static void lbfgs_iteration(const orc_problem *P, const double *logc, const orc_
             if (gpu_store != store) {
                 double cosv = (ns > 0 && ny > 0) ? sy / (ns * ny) : 0.0;
                 double mgn = cosv - C->curv_eps;
-                note_disagreement(sr, fabs(mgn) <= R->tol_curv, mgn, iter, KIND_CURV);
+                /* a step within a few single-precision ulps of x may round to
+                 * no move at all in the compared FP32 run (s = 0, nothing to
+                 * store): its pair decision is borderline whatever the cosine */
+                double srel = 0.0;
+                for (int j = 0; j < d; ++j) srel = fmax(srel, fabs(s[j]) / fmax(fabs(x[j]), 1e-30));
+                int below_fp32 = srel < 0x1p-21;
+                note_disagreement(sr, below_fp32 || fabs(mgn) <= R->tol_curv, mgn, iter, KIND_CURV);
                 store = gpu_store;
             }
         }
@@ -602,6 +608,7 @@ static void lbfgs_iteration(const orc_problem *P, const double *logc, const orc_
 int orc_phase_converge(const orc_problem *P, const double *logc, const orc_config *C, orc_state *S, orc_replay *R)
 {
     int N = C->N, d = P->d, m = C->m;
+    if (C->ls_max < 1 || C->ls_max > 15) return ORC_EINVAL; /* trace codes keep the index in 4 bits, 15 = failed */
     sample_replay_t *sr = (sample_replay_t *)calloc((size_t)N, sizeof(sample_replay_t));
     if (!sr) return ORC_ENOMEM;
     uint8_t *trace = (R && R->trace_out) ? R->trace_out : NULL;
@@ -670,6 +677,7 @@ int orc_lbfgs_iterate(const orc_problem *P, const double *logc, const orc_config
 {
     int N = C->N;
     if (first < 1 || first + n - 1 > C->n_conv) return ORC_EINVAL;
+    if (C->ls_max < 1 || C->ls_max > 15) return ORC_EINVAL;
     sample_replay_t *sr = (sample_replay_t *)calloc((size_t)N, sizeof(sample_replay_t));
     if (!sr) return ORC_ENOMEM;
     uint8_t *trace = (R && R->trace_out) ? R->trace_out : NULL;

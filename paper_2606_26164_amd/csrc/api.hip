@@ -65,7 +65,7 @@ int pad_dim(int d) { return d <= 16 ? 16 : (d <= 32 ? 32 : 64); }
 // (linear, XCD-chunked) x grid (8192 workgroups, dispatched as slots free up;
 // 1024, one resident wave per SIMD looping over tiles).
 constexpr int kTuneVariants = 4;
-constexpr int kMaxTrials = 16;  // upper bound of ls_max
+constexpr int kMaxTrials = 15;  // upper bound of ls_max
 constexpr int kTuneOrder[kTuneVariants] = {0, 1, 0, 1};
 constexpr int kTuneCap[kTuneVariants] = {8192, 8192, 1024, 1024};
 int coords_per_lane(int d) { return d <= 16 ? 1 : (d <= 32 ? 2 : 4); }
@@ -173,7 +173,7 @@ static int validate(const chisao_problem *p, const chisao_config *c, int idx) {
     if (c->n_osc < 1) return fail(CHISAO_E_INVAL, "problem %d: n_osc must be >= 1", idx);
     if (c->n_anti < 0 || c->n_cloud < 0) return fail(CHISAO_E_INVAL, "problem %d: negative step count", idx);
     if (c->M < 1 || c->M > 32) return fail(CHISAO_E_INVAL, "problem %d: M must be in 1..32", idx);
-    if (c->ls_max < 1 || c->ls_max > 16) return fail(CHISAO_E_INVAL, "problem %d: ls_max must be in 1..16", idx);
+    if (c->ls_max < 1 || c->ls_max > 15) return fail(CHISAO_E_INVAL, "problem %d: ls_max must be in 1..15", idx);
     if (c->grad_mode != CHISAO_GRAD_FD && c->grad_mode != CHISAO_GRAD_ADJOINT)
         return fail(CHISAO_E_INVAL, "problem %d: unknown grad_mode", idx);
     if (c->gate_reps < 0 || c->gate_reps > 4096) return fail(CHISAO_E_INVAL, "problem %d: gate_reps must be in 0..4096", idx);
