@@ -953,12 +953,26 @@ __global__ __launch_bounds__(kBlock) void norm_partial_kernel(Dev D, const float
     const int b = pd.s0 + blockIdx.x * chunk, e = min(pd.s0 + pd.N, b + chunk);
     double acc = 0.0, cnt = 0.0;
     if (pd.alpha <= 0.0f) {
-        for (int s = b + wv; s < e; s += kWavesPerBlock) {
-            if (!(D.active[s] && !D.stuck[s])) continue;
-            const float gv = lane < pd.d ? Gs[(size_t)s * D.DS + lane] : 0.0f;
-            const float nn = sqrtf(wave_sum(gv * gv));
-            acc += (double)nn;
-            cnt += 1.0;
+        // four samples per pass, loaded together and added in sample order
+        constexpr int kIlp = 4;
+        for (int s0 = b + wv; s0 < e; s0 += kIlp * kWavesPerBlock) {
+            float nn[kIlp];
+            bool use[kIlp];
+#pragma unroll
+            for (int u = 0; u < kIlp; ++u) {
+                const int s = s0 + u * kWavesPerBlock;
+                use[u] = s < e && D.active[s] && !D.stuck[s];
+                const float gv = (use[u] && lane < pd.d) ? Gs[(size_t)s * D.DS + lane] : 0.0f;
+                nn[u] = gv * gv;
+            }
+#pragma unroll
+            for (int u = 0; u < kIlp; ++u) nn[u] = sqrtf(wave_sum(nn[u]));
+#pragma unroll
+            for (int u = 0; u < kIlp; ++u)
+                if (use[u]) {
+                    acc += (double)nn[u];
+                    cnt += 1.0;
+                }
         }
     }
     if (lane == 0) {
@@ -998,8 +1012,10 @@ __global__ void step_final_kernel(Dev D, int nblocks, int which) {
 }
 
 hipError_t launch_step_size(const Dev &D, const float *Gsrc, int which, hipStream_t st) {
-    hipLaunchKernelGGL(norm_partial_kernel, dim3(D.n_part_blocks, D.P), dim3(kBlock), 0, st, D, Gsrc);
-    hipLaunchKernelGGL(step_final_kernel, dim3(grid_for(D.P, 64)), dim3(64), 0, st, D, D.n_part_blocks, which);
+    // 256 blocks per problem (2 partials each: within the partial buffer)
+    constexpr int kNormBlocks = 256;
+    hipLaunchKernelGGL(norm_partial_kernel, dim3(kNormBlocks, D.P), dim3(kBlock), 0, st, D, Gsrc);
+    hipLaunchKernelGGL(step_final_kernel, dim3(grid_for(D.P, 64)), dim3(64), 0, st, D, kNormBlocks, which);
     return hipGetLastError();
 }
 
