@@ -193,3 +193,36 @@ def test_config4_batch_stuck_points_are_stationary_and_gated():
     print(f"\nconfig4: {len(items)} problems in {dt:.1f} s; {n_pts} points recovered: {n_max} distinct maxima, "
           f"{n_saddle} saddles, {n_dup} further copies of a maximum; significant modes recovered {hit}/{sig}")
     assert n_max >= 0.9 * n_pts
+
+
+def test_config5_noisy_student_t_full_run():
+    """Config 5 at full size: d=32 Student-t mixture (K=48, nu=3), unit noise on
+    every evaluation, N=131072, 400 cycles, M=32 probes at sigma=0.2, gate over
+    32 draws.  Every recovered point is stationary in FP64 and inside its own
+    gate; recall of the significant set and the peak error are reported."""
+    from oracle.modes import newton_modes, value_grad_hess
+    from paper_2606_26164_amd.api import Optimizer
+
+    prob, cfg, x0 = W.config5()
+    Xall, Fall = newton_modes(prob, log_delta=None)
+    tol_all = _tolerances(prob, Xall, cfg.eps_grad)
+    t = time.perf_counter()
+    with Optimizer(prob, cfg, x0) as opt:
+        stats = opt.cycle(cfg.n_osc, stats=True)
+        ms = opt.modes()
+    dt = time.perf_counter() - t
+    X = ms.X.astype(np.float64)
+    for x in X:
+        _, gx, _ = value_grad_hess(prob, x)
+        assert np.abs(gx).max() < 2 * cfg.eps_grad
+    keep = Fall >= Fall.max() + cfg.log_delta
+    recall, _ = _score(X, Xall[keep], tol_all[keep])
+    _, not_a_max = _score(X, Xall, tol_all)
+    err = [np.abs(Xall - x).max(1).min() for x in X]
+    print(f"\nconfig5: {len(X)} modes in {dt:.1f} s ({dt / cfg.n_osc * 1e3:.1f} ms/cycle); significant set "
+          f"{keep.sum()}, recall {recall:.3f}; points that are no distinct maximum {not_a_max}; "
+          f"peak error max {max(err) if err else 0:.2e}; f_max {stats[-1]['f_max']:.3f}")
+    print(_report(prob, X, ms.F, Xall, Fall))
+    assert len(X) >= 1
+    if len(ms.F):
+        assert ms.F.min() >= stats[-1]["f_max"] + cfg.log_delta - 1e-5
