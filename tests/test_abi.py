@@ -40,21 +40,16 @@ def test_ctypes_struct_layouts_match_header():
 
     from paper_2606_26164_amd import _lib
 
-    src = r'''
-#include <stddef.h>
-#include <stdio.h>
-#include "chisao.h"
-#define P(T, f) printf(#T " " #f " %zu\n", offsetof(T, f));
-int main(void) {
-  printf("chisao_problem size %zu\n", sizeof(chisao_problem));
-  printf("chisao_config size %zu\n", sizeof(chisao_config));
-  printf("chisao_cycle_stats size %zu\n", sizeof(chisao_cycle_stats));
-  printf("chisao_state size %zu\n", sizeof(chisao_state));
-  P(chisao_problem, noise_sigma) P(chisao_config, seed) P(chisao_config, problem_id)
-  P(chisao_config, phase_mask) P(chisao_cycle_stats, evals) P(chisao_state, k) P(chisao_state, gr_prev_modes)
-  return 0;
-}
-'''
+    m = {"chisao_problem": _lib.Problem, "chisao_config": _lib.Config, "chisao_cycle_stats": _lib.CycleStats,
+         "chisao_state": _lib.State, "chisao_kernel_profile": _lib.KernelProfile,
+         "chisao_tuning_entry": _lib.TuningEntry}
+    lines = []
+    for t, cls in m.items():
+        lines.append(f'  printf("{t} size %zu\\n", sizeof({t}));')
+        lines += [f"  P({t}, {f})" for f, _ in cls._fields_]
+    src = ("#include <stddef.h>\n#include <stdio.h>\n#include \"chisao.h\"\n"
+           "#define P(T, f) printf(#T \" \" #f \" %zu\\n\", offsetof(T, f));\n"
+           "int main(void) {\n" + "\n".join(lines) + "\n  return 0;\n}\n")
     with tempfile.TemporaryDirectory() as td:
         c = os.path.join(td, "l.c")
         open(c, "w").write(src)
@@ -66,8 +61,7 @@ int main(void) {
         if ln.strip():
             t, f, v = ln.split()
             got[(t, f)] = int(v)
-    m = {"chisao_problem": _lib.Problem, "chisao_config": _lib.Config, "chisao_cycle_stats": _lib.CycleStats,
-         "chisao_state": _lib.State}
+    assert len(got) == sum(len(c._fields_) + 1 for c in m.values())
     for (t, f), v in got.items():
         cls = m[t]
         if f == "size":
