@@ -41,18 +41,30 @@ extern "C" {
 
 #define CHISAO_GAUSS 0     /* Gaussian mixture log-density (Appendix D, with full precision matrices) */
 #define CHISAO_STUDENT_T 1 /* multivariate Student-t mixture log-density */
+/* Closed-form test functions of Appendix D, each negated so that its optimum
+ * is a maximum (constants as stated there: Rastrigin A = 10; Ackley a = 20,
+ * b = 0.2, c = 2 pi; Michalewicz m = 10).  Coordinate i of the paper is x[i-1]. */
+#define CHISAO_RASTRIGIN 2       /* -[10 d + sum (x_i^2 - 10 cos(2 pi x_i))] */
+#define CHISAO_ACKLEY 3          /* 20 exp(-0.2 sqrt(mean x_i^2)) + exp(mean cos(2 pi x_i)) - 20 - e */
+#define CHISAO_SCHWEFEL 4        /* -[418.9829 d - sum x_i sin(sqrt|x_i|)] */
+#define CHISAO_STYBLINSKI_TANG 5 /* -1/2 sum (x_i^4 - 16 x_i^2 + 5 x_i) */
+#define CHISAO_MICHALEWICZ 6     /* sum sin(x_i) sin^20(i x_i^2 / pi) */
+#define CHISAO_TRID 7            /* -[sum (x_i - 1)^2 - sum_{i>=2} x_i x_{i-1}] */
+#define CHISAO_BUKIN6 8          /* -[100 sqrt|x_2 - 0.01 x_1^2| + 0.01 |x_1 + 10|], d = 2 */
 
 #define CHISAO_GRAD_FD 0      /* central finite differences, 2d evaluations per gradient (Sec. 3.1, Sec. 5) */
-#define CHISAO_GRAD_ADJOINT 1 /* analytic reverse-mode gradient fused with the value */
+#define CHISAO_GRAD_ADJOINT 1 /* analytic gradient fused with the value (reverse mode for the mixtures) */
 
-/* Mixture objective f(x) = log sum_k w_k p_k(x) on the box [lo, hi].
- * p_k is N(mu_k, prec_k^-1) (Gaussian) or the Student-t density with nu
- * degrees of freedom and scale matrix prec_k^-1.  All arrays are host memory,
- * copied by chisao_init. */
+/* Objective on the box [lo, hi]: a mixture f(x) = log sum_k w_k p_k(x), with
+ * p_k N(mu_k, prec_k^-1) (Gaussian) or the Student-t density with nu degrees
+ * of freedom and scale matrix prec_k^-1; or one of the closed-form test
+ * functions, for which K, nu, log_w, mu and prec are ignored (the arrays may
+ * be NULL) and the box is the caller's (Appendix D gives each function's).
+ * All arrays are host memory, copied by chisao_init. */
 typedef struct {
-    int32_t family;      /* CHISAO_GAUSS or CHISAO_STUDENT_T */
-    int32_t d;           /* dimension, 1..64 */
-    int32_t K;           /* number of components, >= 1 */
+    int32_t family;      /* CHISAO_GAUSS, CHISAO_STUDENT_T or a closed form CHISAO_RASTRIGIN..CHISAO_BUKIN6 */
+    int32_t d;           /* dimension, 1..64 (2 for CHISAO_BUKIN6) */
+    int32_t K;           /* number of components, >= 1 (mixtures only) */
     float nu;            /* Student-t degrees of freedom (> 0), ignored for Gaussians */
     const float *log_w;  /* [K] log mixture weights */
     const float *mu;     /* [K*d] component centres */

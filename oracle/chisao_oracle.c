@@ -43,8 +43,13 @@ enum { PH_INIT = 0, PH_RM = 4, PH_GR = 5, PH_HLC = 6, PH_NOISE = 7, PH_GATE = 8 
 #define TR_CONV 0x20      /* converged after this iteration */
 #define TR_RESET 0x40     /* direction was not an ascent direction: history cleared */
 
+/* Objective families: the two mixture log-densities, then the closed-form
+ * test functions of Appendix D. */
+enum { FAM_GAUSS = 0, FAM_STUDENT_T = 1, FAM_RASTRIGIN = 2, FAM_ACKLEY = 3, FAM_SCHWEFEL = 4,
+       FAM_STYBLINSKI_TANG = 5, FAM_MICHALEWICZ = 6, FAM_TRID = 7, FAM_BUKIN6 = 8 };
+
 typedef struct {
-    int32_t family;   /* 0 Gaussian mixture, 1 Student-t mixture */
+    int32_t family;   /* FAM_*; the closed forms ignore K, nu, log_w, mu and prec */
     int32_t d, K;
     double nu;        /* Student-t degrees of freedom */
     const double *log_w; /* K    log mixture weights */
@@ -167,6 +172,8 @@ static uint32_t uint_below(uint32_t a, uint32_t n) { return (uint32_t)(((uint64_
 int orc_prepare(const orc_problem *P, double *logc)
 {
     int d = P->d, K = P->K;
+    if (P->family >= FAM_RASTRIGIN && P->family <= FAM_BUKIN6)
+        return (d < 1 || (P->family == FAM_BUKIN6 && d != 2)) ? ORC_EINVAL : ORC_OK;
     if (d < 1 || K < 1) return ORC_EINVAL;
     double *L = (double *)malloc(sizeof(double) * (size_t)d * d);
     if (!L) return ORC_ENOMEM;
@@ -201,9 +208,107 @@ int orc_prepare(const orc_problem *P, double *logc)
     return ORC_OK;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Closed-form test functions (Appendix D, each already negated so that the  */
+/* optimum is a maximum) and their analytic gradients.  Coordinates are      */
+/* numbered from 1 in the paper; x[i-1] here.  Where a function is not       */
+/* differentiable (Ackley at the origin, Bukin N.6 on its ridge, |.| at 0)   */
+/* the gradient term is taken as 0.                                          */
+/* ------------------------------------------------------------------------ */
+static double sgn(double v) { return (v > 0.0) - (v < 0.0); }
+
+static double closed_form(int family, int d, const double *x, double *g)
+{
+    const double two_pi = 2.0 * M_PI;
+    switch (family) {
+    case FAM_RASTRIGIN: {
+        /* -[A d + sum (x_i^2 - A cos(2 pi x_i))], A = 10 */
+        const double A = 10.0;
+        double s = A * d;
+        for (int i = 0; i < d; ++i) {
+            s += x[i] * x[i] - A * cos(two_pi * x[i]);
+            if (g) g[i] = -(2.0 * x[i] + two_pi * A * sin(two_pi * x[i]));
+        }
+        return -s;
+    }
+    case FAM_ACKLEY: {
+        /* -[-a exp(-b sqrt(mean x_i^2)) - exp(mean cos(c x_i)) + a + e],
+         * a = 20, b = 0.2, c = 2 pi */
+        const double a = 20.0, b = 0.2, c = two_pi;
+        double sq = 0.0, sc = 0.0;
+        for (int i = 0; i < d; ++i) {
+            sq += x[i] * x[i];
+            sc += cos(c * x[i]);
+        }
+        double r = sqrt(sq / d), ea = exp(-b * r), ec = exp(sc / d);
+        if (g)
+            for (int i = 0; i < d; ++i)
+                g[i] = (r > 0.0 ? -a * b * ea * x[i] / (d * r) : 0.0) - ec * c * sin(c * x[i]) / d;
+        return -(-a * ea - ec + a + M_E);
+    }
+    case FAM_SCHWEFEL: {
+        /* -[418.9829 d - sum x_i sin(sqrt|x_i|)] */
+        double s = 418.9829 * d;
+        for (int i = 0; i < d; ++i) {
+            double r = sqrt(fabs(x[i]));
+            s -= x[i] * sin(r);
+            /* d/dx [x sin sqrt|x|] = sin r + x cos(r) sgn(x) / (2 r) = sin r + (r/2) cos r */
+            if (g) g[i] = sin(r) + 0.5 * r * cos(r);
+        }
+        return -s;
+    }
+    case FAM_STYBLINSKI_TANG: {
+        /* -1/2 sum (x_i^4 - 16 x_i^2 + 5 x_i) */
+        double s = 0.0;
+        for (int i = 0; i < d; ++i) {
+            double v = x[i];
+            s += v * v * v * v - 16.0 * v * v + 5.0 * v;
+            if (g) g[i] = -0.5 * (4.0 * v * v * v - 32.0 * v + 5.0);
+        }
+        return -0.5 * s;
+    }
+    case FAM_MICHALEWICZ: {
+        /* sum sin(x_i) sin^(2m)(i x_i^2 / pi), m = 10 */
+        const int two_m = 20;
+        double s = 0.0;
+        for (int i = 0; i < d; ++i) {
+            double v = x[i], u = (i + 1) * v * v / M_PI, su = sin(u);
+            s += sin(v) * pow(su, two_m);
+            if (g)
+                g[i] = cos(v) * pow(su, two_m) +
+                       sin(v) * two_m * pow(su, two_m - 1) * cos(u) * (2.0 * (i + 1) * v / M_PI);
+        }
+        return s;
+    }
+    case FAM_TRID: {
+        /* -[sum (x_i - 1)^2 - sum_{i>=2} x_i x_{i-1}] */
+        double s = 0.0;
+        for (int i = 0; i < d; ++i) s += (x[i] - 1.0) * (x[i] - 1.0);
+        for (int i = 1; i < d; ++i) s -= x[i] * x[i - 1];
+        if (g)
+            for (int i = 0; i < d; ++i)
+                g[i] = -2.0 * (x[i] - 1.0) + (i > 0 ? x[i - 1] : 0.0) + (i + 1 < d ? x[i + 1] : 0.0);
+        return -s;
+    }
+    case FAM_BUKIN6: {
+        /* -[100 sqrt|y - 0.01 x^2| + 0.01 |x + 10|], (x, y) = (x[0], x[1]) */
+        double u = x[1] - 0.01 * x[0] * x[0], r = sqrt(fabs(u));
+        if (g) {
+            double w = r > 0.0 ? sgn(u) / r : 0.0; /* d sqrt|u| / du = sgn(u) / (2 r) */
+            g[0] = -(100.0 * 0.5 * w * (-0.02 * x[0]) + 0.01 * sgn(x[0] + 10.0));
+            g[1] = -(100.0 * 0.5 * w);
+        }
+        return -(100.0 * r + 0.01 * fabs(x[0] + 10.0));
+    }
+    default:
+        return NAN;
+    }
+}
+
 /* f(x) and, if g != NULL, its gradient.  work holds K + K*d doubles. */
 static double eval_point(const orc_problem *P, const double *logc, const double *x, double *g, double *work)
 {
+    if (P->family >= FAM_RASTRIGIN) return closed_form(P->family, P->d, x, g);
     int d = P->d, K = P->K;
     double *lk = work;           /* K log terms */
     double *U = work + K;        /* K*d: P_k (x - mu_k) */
@@ -247,7 +352,10 @@ static double eval_point(const orc_problem *P, const double *logc, const double 
     return f;
 }
 
-static size_t eval_work_len(const orc_problem *P) { return (size_t)P->K * (1 + P->d); }
+static size_t eval_work_len(const orc_problem *P)
+{
+    return P->family >= FAM_RASTRIGIN ? 1 : (size_t)P->K * (1 + P->d);
+}
 
 /* ------------------------------------------------------------------------ */
 /* Likelihood noise (Sec. 5.7): every evaluation the method makes returns    */

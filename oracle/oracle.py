@@ -23,6 +23,8 @@ TR_LS_FAIL = 0x0F
 TR_STORED = 0x10
 TR_CONV = 0x20
 TR_RESET = 0x40
+# objective families from 2 on are the closed-form test functions of Appendix D
+CLOSED_FORM_FIRST = 2
 
 
 def build(force: bool = False) -> str:
@@ -131,16 +133,20 @@ class OracleProblem:
         self.d, self.K, self.family = prob.d, prob.K, prob.family
         if self.d > 512:
             raise ValueError("oracle supports d <= 512")
-        self.log_w = np.ascontiguousarray(prob.log_w, dtype=np.float64)
-        self.mu = np.ascontiguousarray(prob.mu, dtype=np.float64).reshape(self.K, self.d)
-        self.prec = np.ascontiguousarray(prob.prec, dtype=np.float64).reshape(self.K, self.d, self.d)
+        if self.family >= CLOSED_FORM_FIRST:
+            # closed-form test function: no mixture arrays
+            self.K = 0
+        self.log_w = np.ascontiguousarray(prob.log_w if self.K else np.zeros(0), dtype=np.float64)
+        self.mu = np.ascontiguousarray(prob.mu if self.K else np.zeros(0), dtype=np.float64).reshape(self.K, self.d)
+        self.prec = np.ascontiguousarray(prob.prec if self.K else np.zeros(0),
+                                         dtype=np.float64).reshape(self.K, self.d, self.d)
         self.lo = np.ascontiguousarray(prob.lo, dtype=np.float64)
         self.hi = np.ascontiguousarray(prob.hi, dtype=np.float64)
         self.nu = float(prob.nu)
         self.noise_sigma = float(prob.noise_sigma)
         self.c = _Problem(self.family, self.d, self.K, self.nu, _ptr(self.log_w), _ptr(self.mu), _ptr(self.prec),
                           _ptr(self.lo), _ptr(self.hi), self.noise_sigma)
-        self.logc = np.zeros(self.K)
+        self.logc = np.zeros(max(self.K, 1))
         rc = lib().orc_prepare(C.byref(self.c), _ptr(self.logc))
         if rc != 0:
             raise ValueError(f"orc_prepare failed ({rc}): precision matrix not positive definite?")
@@ -160,8 +166,16 @@ class OracleProblem:
         return G
 
 
-def make_config(cfg) -> _Config:
-    return _Config(cfg.N, cfg.m, cfg.n_osc, cfg.n_conv, cfg.n_anti, cfg.n_cloud, cfg.M, cfg.eps_grad,
+def conv_steps(cfg, d: int) -> int:
+    """n_conv, with the Table 1 default max(10, 3 log2 d) when it is not given
+    (3 log2 d rounded up)."""
+    if cfg.n_conv > 0:
+        return int(cfg.n_conv)
+    return max(10, int(np.ceil(3.0 * np.log2(d) - 1e-9)))
+
+
+def make_config(cfg, d: int) -> _Config:
+    return _Config(cfg.N, cfg.m, cfg.n_osc, conv_steps(cfg, d), cfg.n_anti, cfg.n_cloud, cfg.M, cfg.eps_grad,
                    cfg.eps_dup, cfg.log_delta, cfg.momentum, cfg.alpha, cfg.sigma, cfg.sigma_c, cfg.grad_mode,
                    cfg.fd_h, cfg.ls_c1, cfg.ls_max, cfg.curv_eps, cfg.gate_reps, cfg.phase_mask, cfg.seed,
                    cfg.problem_id)
@@ -187,7 +201,7 @@ class OracleRun:
     def __init__(self, prob, cfg, x0: np.ndarray | None = None):
         self.P = prob if isinstance(prob, OracleProblem) else OracleProblem(prob)
         self.cfg = cfg
-        self.cc = make_config(cfg)
+        self.cc = make_config(cfg, self.P.d)
         N, d, m = cfg.N, self.P.d, cfg.m
         self.X = np.zeros((N, d))
         if x0 is None:
@@ -206,7 +220,7 @@ class OracleRun:
         self.rho = np.zeros((N, m))
         self.head = np.full(N, m - 1, np.int32)
         self.cnt = np.zeros(N, np.int32)
-        self.trace = np.full((cfg.n_conv + 1, N), TR_NONE, np.uint8)
+        self.trace = np.full((self.cc.n_conv + 1, N), TR_NONE, np.uint8)
         self.Fg = np.zeros(N)
         self.st = _State(_ptr(self.X), _ptr(self.F), _ptr(self.G), _ptr(self.V), _ptr(self.stuck),
                          _ptr(self.active), _ptr(self.conv), _ptr(self.removed), _ptr(self.S), _ptr(self.Y),

@@ -141,17 +141,19 @@ static hipError_t timed(chisao_ctx *h, int cls, F &&launch) {
 // ---------------------------------------------------------------------------
 static int validate(const chisao_problem *p, const chisao_config *c, int idx) {
     if (!p || !c) return fail(CHISAO_E_INVAL, "null problem or config");
-    if (p->family != CHISAO_GAUSS && p->family != CHISAO_STUDENT_T)
-        return fail(CHISAO_E_INVAL, "problem %d: unknown family", idx);
+    if (p->family < CHISAO_GAUSS || p->family > CHISAO_BUKIN6)
+        return fail(CHISAO_E_INVAL, "problem %d: unknown family %d", idx, p->family);
+    const bool closed = p->family >= CHISAO_RASTRIGIN;
     if (p->d < 1 || p->d > 64) return fail(CHISAO_E_INVAL, "problem %d: d must be in 1..64 (got %d)", idx, p->d);
-    if (p->K < 1) return fail(CHISAO_E_INVAL, "problem %d: K must be >= 1", idx);
-    if (!p->log_w || !p->mu || !p->prec || !p->lo || !p->hi)
+    if (p->family == CHISAO_BUKIN6 && p->d != 2) return fail(CHISAO_E_INVAL, "problem %d: Bukin N.6 needs d = 2", idx);
+    if (!closed && p->K < 1) return fail(CHISAO_E_INVAL, "problem %d: K must be >= 1", idx);
+    if ((!closed && (!p->log_w || !p->mu || !p->prec)) || !p->lo || !p->hi)
         return fail(CHISAO_E_INVAL, "problem %d: null problem array", idx);
     if (p->family == CHISAO_STUDENT_T && !(p->nu > 0.0f && isfinite(p->nu)))
         return fail(CHISAO_E_INVAL, "problem %d: Student-t needs nu > 0", idx);
     if (!(p->noise_sigma >= 0.0f && isfinite(p->noise_sigma)))
         return fail(CHISAO_E_INVAL, "problem %d: noise_sigma must be finite and >= 0", idx);
-    const int d = p->d, K = p->K;
+    const int d = p->d, K = closed ? 0 : p->K;
     for (int j = 0; j < d; ++j)
         if (!(isfinite(p->lo[j]) && isfinite(p->hi[j]) && p->lo[j] < p->hi[j]))
             return fail(CHISAO_E_INVAL, "problem %d: box bounds must be finite with lo < hi (coordinate %d)", idx, j);
@@ -282,29 +284,35 @@ extern "C" int chisao_init_batched(chisao_handle *out, int n_problems, const chi
         for (int p = 0; p < n_problems; ++p) {
             const chisao_problem &pr = ps[p];
             const chisao_config &c = cs[p];
-            const size_t d = pr.d, K = pr.K, DP = pad_dim(pr.d);
+            // closed-form functions have no component arrays
+            const bool closed = pr.family >= CHISAO_RASTRIGIN;
+            const size_t d = pr.d, K = closed ? 0 : pr.K, DP = pad_dim(pr.d);
             ProblemDesc &q = h->pdh[p];
             memset(&q, 0, sizeof q);
-            float *Pfrag, *muB, *muC, *logc2, *lo, *hi, *tw, *tmu, *tprec;
-            ALLOC(Pfrag, float, K * DP * DP);
-            ALLOC(muB, float, K * DP);
-            ALLOC(muC, float, K * DP);
-            ALLOC(logc2, float, K);
+            float *Pfrag = nullptr, *muB = nullptr, *muC = nullptr, *logc2 = nullptr, *lo, *hi;
             ALLOC(lo, float, d);
             ALLOC(hi, float, d);
-            ALLOC(tw, float, K);
-            ALLOC(tmu, float, K * d);
-            ALLOC(tprec, float, K * d * d);
             HIP_GO(hipMemcpyAsync(lo, pr.lo, sizeof(float) * d, hipMemcpyHostToDevice, st));
             HIP_GO(hipMemcpyAsync(hi, pr.hi, sizeof(float) * d, hipMemcpyHostToDevice, st));
-            HIP_GO(hipMemcpyAsync(tw, pr.log_w, sizeof(float) * K, hipMemcpyHostToDevice, st));
-            HIP_GO(hipMemcpyAsync(tmu, pr.mu, sizeof(float) * K * d, hipMemcpyHostToDevice, st));
-            HIP_GO(hipMemcpyAsync(tprec, pr.prec, sizeof(float) * K * d * d, hipMemcpyHostToDevice, st));
             const float nu = pr.family == CHISAO_STUDENT_T ? pr.nu : 1.0f;
-            HIP_GO(launch_prepare(pr.family, pr.d, (int)DP, pr.K, nu, tw, tmu, tprec, logc2, Pfrag, muB, muC, bad, st));
+            if (!closed) {
+                float *tw, *tmu, *tprec;
+                ALLOC(Pfrag, float, K * DP * DP);
+                ALLOC(muB, float, K * DP);
+                ALLOC(muC, float, K * DP);
+                ALLOC(logc2, float, K);
+                ALLOC(tw, float, K);
+                ALLOC(tmu, float, K * d);
+                ALLOC(tprec, float, K * d * d);
+                HIP_GO(hipMemcpyAsync(tw, pr.log_w, sizeof(float) * K, hipMemcpyHostToDevice, st));
+                HIP_GO(hipMemcpyAsync(tmu, pr.mu, sizeof(float) * K * d, hipMemcpyHostToDevice, st));
+                HIP_GO(hipMemcpyAsync(tprec, pr.prec, sizeof(float) * K * d * d, hipMemcpyHostToDevice, st));
+                HIP_GO(launch_prepare(pr.family, pr.d, (int)DP, pr.K, nu, tw, tmu, tprec, logc2, Pfrag, muB, muC, bad,
+                                      st));
+            }
             q.d = pr.d;
             q.DP = (int)DP;
-            q.K = pr.K;
+            q.K = (int)K;
             q.family = pr.family;
             q.nu = nu;
             q.nu_plus_d = nu + (float)pr.d;

@@ -4,9 +4,13 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "chisao.h"
+
 namespace chisao {
 
 constexpr int kWave = 64;
+// objective families from here on are closed-form test functions
+constexpr int kFamClosed = CHISAO_RASTRIGIN;
 
 // ---------------------------------------------------------------------------
 // Counter-based random streams: Philox4x32-10 (Salmon, Moraes, Dror, Shaw,

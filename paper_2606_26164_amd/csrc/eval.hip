@@ -17,6 +17,10 @@
 // u[point l%16][16mb + 4(l/16) + r], r = 0..3.  Components are streamed; the
 // log-sum-exp runs online in base 2 (one rescale per wave only when some
 // lane's running maximum moves).
+//
+// The closed-form test functions of Appendix D share the kernel's tiling,
+// point generation and epilogues; their value (and analytic gradient) is a
+// sum over coordinates evaluated on the VALU, two lanes per point.
 #include <math.h>
 
 #include "kernels.h"
@@ -60,12 +64,121 @@ struct CompRegs {
     float lc2;
 };
 
+// ---------------------------------------------------------------------------
+// Closed-form test functions (Appendix D; each negated so that its optimum is
+// a maximum).  cf_partial sums one lane's share of the coordinates, c = c0,
+// c0 + 2, ... < d, into two accumulators (Ackley needs two sums, the others
+// one); cf_value turns the totals into f; cf_grad gives df/dx_c from the
+// totals.  Non-differentiable points (Ackley's origin, Bukin N.6's ridge)
+// get a zero gradient term.
+// ---------------------------------------------------------------------------
+constexpr float kTwoPi = 6.283185307179586f;
+constexpr float kInvPi = 0.3183098861837907f;
+
+__device__ __forceinline__ float sign_of(float v) { return (float)((v > 0.0f) - (v < 0.0f)); }
+
+// sin(u)^20 and sin(u)^19 (Michalewicz, m = 10)
+__device__ __forceinline__ void pow20(float su, float &p20, float &p19) {
+    const float s2 = su * su, s4 = s2 * s2, s8 = s4 * s4, s16 = s8 * s8;
+    p20 = s16 * s4;
+    p19 = s16 * s2 * su;
+}
+
+__device__ __forceinline__ void cf_partial(int fam, int d, const float *x, int c0, float &a, float &b) {
+    a = 0.0f;
+    b = 0.0f;
+    switch (fam) {
+        case CHISAO_RASTRIGIN:
+            for (int c = c0; c < d; c += 2) a += x[c] * x[c] - 10.0f * cospif(2.0f * x[c]);
+            break;
+        case CHISAO_ACKLEY:
+            for (int c = c0; c < d; c += 2) {
+                a += x[c] * x[c];
+                b += cospif(2.0f * x[c]);
+            }
+            break;
+        case CHISAO_SCHWEFEL:
+            for (int c = c0; c < d; c += 2) a += x[c] * sinf(sqrtf(fabsf(x[c])));
+            break;
+        case CHISAO_STYBLINSKI_TANG:
+            for (int c = c0; c < d; c += 2) {
+                const float v = x[c], v2 = v * v;
+                a += v2 * v2 - 16.0f * v2 + 5.0f * v;
+            }
+            break;
+        case CHISAO_MICHALEWICZ:
+            for (int c = c0; c < d; c += 2) {
+                const float v = x[c];
+                float p20, p19;
+                pow20(sinf((float)(c + 1) * v * v * kInvPi), p20, p19);
+                a += sinf(v) * p20;
+            }
+            break;
+        case CHISAO_TRID:
+            for (int c = c0; c < d; c += 2) {
+                a += (x[c] - 1.0f) * (x[c] - 1.0f);
+                if (c > 0) b += x[c] * x[c - 1];
+            }
+            break;
+        case CHISAO_BUKIN6:
+            if (c0 == 0) a = 100.0f * sqrtf(fabsf(x[1] - 0.01f * x[0] * x[0])) + 0.01f * fabsf(x[0] + 10.0f);
+            break;
+    }
+}
+
+__device__ __forceinline__ float cf_value(int fam, int d, float a, float b) {
+    switch (fam) {
+        case CHISAO_RASTRIGIN: return -(10.0f * (float)d + a);
+        case CHISAO_ACKLEY: {
+            const float r = sqrtf(a / (float)d);
+            return 20.0f * expf(-0.2f * r) + expf(b / (float)d) - 20.0f - 2.718281828459045f;
+        }
+        case CHISAO_SCHWEFEL: return -(418.9829f * (float)d - a);
+        case CHISAO_STYBLINSKI_TANG: return -0.5f * a;
+        case CHISAO_MICHALEWICZ: return a;
+        case CHISAO_TRID: return -(a - b);
+        case CHISAO_BUKIN6: return -a;
+        default: return __builtin_nanf("");
+    }
+}
+
+__device__ __forceinline__ float cf_grad(int fam, int d, const float *x, int c, float a, float b) {
+    const float v = x[c];
+    switch (fam) {
+        case CHISAO_RASTRIGIN: return -(2.0f * v + 10.0f * kTwoPi * sinpif(2.0f * v));
+        case CHISAO_ACKLEY: {
+            const float r = sqrtf(a / (float)d);
+            const float t1 = r > 0.0f ? -20.0f * 0.2f * expf(-0.2f * r) * v / ((float)d * r) : 0.0f;
+            return t1 - expf(b / (float)d) * kTwoPi * sinpif(2.0f * v) / (float)d;
+        }
+        case CHISAO_SCHWEFEL: {
+            const float r = sqrtf(fabsf(v));
+            return sinf(r) + 0.5f * r * cosf(r);
+        }
+        case CHISAO_STYBLINSKI_TANG: return -0.5f * (4.0f * v * v * v - 32.0f * v + 5.0f);
+        case CHISAO_MICHALEWICZ: {
+            const float ci = (float)(c + 1), u = ci * v * v * kInvPi;
+            float p20, p19;
+            pow20(sinf(u), p20, p19);
+            return cosf(v) * p20 + sinf(v) * 20.0f * p19 * cosf(u) * (2.0f * ci * v * kInvPi);
+        }
+        case CHISAO_TRID:
+            return -2.0f * (v - 1.0f) + (c > 0 ? x[c - 1] : 0.0f) + (c + 1 < d ? x[c + 1] : 0.0f);
+        case CHISAO_BUKIN6: {
+            const float u = x[1] - 0.01f * x[0] * x[0], r = sqrtf(fabsf(u));
+            const float w = r > 0.0f ? sign_of(u) / r : 0.0f;  // d sqrt|u| / du = w / 2
+            return c == 0 ? x[0] * w - 0.01f * sign_of(x[0] + 10.0f) : -50.0f * w;
+        }
+        default: return __builtin_nanf("");
+    }
+}
+
 constexpr int kMaxClass = 256;  // problems per class (LDS budget: 2 waves per SIMD)
 // waves per line-search tile: at DP = 64 a tile's pass over the components is
 // long enough to be worth splitting; smaller components are cheap per tile
 // and the merge would only add work
-template <int DP>
-constexpr int trial_split() { return DP == 64 ? 4 : 1; }
+template <int DP, int FAM>
+constexpr int trial_split() { return DP == 64 && FAM < kFamClosed ? 4 : 1; }
 
 __device__ __forceinline__ int job_count(const EvalArgs &a, int p, const ProblemDesc &pd) {
     if (a.ext_n >= 0) return a.ext_n;
@@ -106,6 +219,7 @@ template <int DP, int FAM, bool GRAD, int CENTER, bool FD, int SPLIT>
 __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2))) void eval_kernel(EvalArgs a) {
     constexpr int KS = DP / 4;
     constexpr int MB = DP / 16;
+    constexpr bool CLOSED = FAM >= kFamClosed;
     constexpr int LD = DP + 1;  // padded row: conflict-free column reads
     constexpr int NP = SPLIT > 1 ? SPLIT - 1 : 1;
     __shared__ float s_pm[NP][NB][kWave], s_ps[NP][NB][kWave];       // partial max / sum of waves 1..
@@ -254,214 +368,233 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
             for (int q = 0; q < 4; ++q) s_pts[pt * LD + c0 + q] = x[q];
         }
         __syncthreads();
-        // ---- operand registers ---------------------------------------------
-        float xB[NB][KS], xC[NB][KS];
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-            const float *row = s_pts + (nb * 16 + n) * LD;
-#pragma unroll
-            for (int ks = 0; ks < KS; ++ks) xB[nb][ks] = row[4 * ks + g];
-#pragma unroll
-            for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) xC[nb][mb * 4 + r] = row[16 * mb + 4 * g + r];
-        }
-        float mrun[NB], srun[NB];
-        float gacc[NB][GRAD ? KS : 1];
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-            mrun[nb] = -INFINITY;
-            srun[nb] = 0.0f;
-            if constexpr (GRAD)
-#pragma unroll
-                for (int i = 0; i < KS; ++i) gacc[nb][i] = 0.0f;
-        }
-        // ---- stream the components -----------------------------------------
-        // Two waves per SIMD: while one waits for a component's operands or
-        // works through the log-sum-exp epilogue on the VALU, the other keeps
-        // the matrix core busy; a wave raises its priority for the duration of
-        // its MFMA block so the arbiter keeps the matrix core fed.  Operands
-        // come through global-address-space pointers: flat loads would also
-        // count against the LDS counter, and the cross-lane reductions of the
-        // epilogue would then wait for them.
-        const gfloat *Pfrag = as_global(pd.Pfrag), *muBk = as_global(pd.muB), *muCk = as_global(pd.muC),
-                     *logc2 = as_global(pd.logc2);
-        const float nu = pd.nu, nupd = pd.nu_plus_d;
-        CompRegs<KS, MB> ra;
-        auto load = [&](int k, CompRegs<KS, MB> &r) {
-            const gfloat *pf = Pfrag + (size_t)k * KS * kWave * MB + lane * MB;
-            const gfloat *mb_p = muBk + ((size_t)k * 4 + g) * KS;
-#pragma unroll
-            for (int ks = 0; ks < KS; ++ks) load_frag<MB>(pf + (size_t)ks * kWave * MB, r.pa[ks]);
-#pragma unroll
-            for (int i = 0; i < KS; i += 4) {
-                const f32x4 vb = *reinterpret_cast<const gf32x4 *>(mb_p + i);
-                r.muB[i] = vb[0]; r.muB[i + 1] = vb[1]; r.muB[i + 2] = vb[2]; r.muB[i + 3] = vb[3];
-            }
-            r.lc2 = logc2[k];
-        };
-        auto step = [&](int k, const CompRegs<KS, MB> &r) {
-            f32x4 acc[NB][MB];
-#pragma unroll
-            for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-                for (int mb = 0; mb < MB; ++mb) acc[nb][mb] = f32x4{0.f, 0.f, 0.f, 0.f};
-            __builtin_amdgcn_s_setprio(1);
-#pragma unroll
-            for (int ks = 0; ks < KS; ++ks) {
-#pragma unroll
-                for (int nb = 0; nb < NB; ++nb) {
-                    const float b = xB[nb][ks] - r.muB[ks];
-#pragma unroll
-                    for (int mb = 0; mb < MB; ++mb)
-                        acc[nb][mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(r.pa[ks][mb], b, acc[nb][mb], 0, 0, 0);
-                }
-            }
-            __builtin_amdgcn_s_setprio(0);
-            // centre coordinates in accumulator-lane order, only needed now
-            float muC[KS];
-            const gfloat *mc_p = muCk + ((size_t)k * 4 + g) * KS;
-#pragma unroll
-            for (int i = 0; i < KS; i += 4) {
-                const f32x4 vc = *reinterpret_cast<const gf32x4 *>(mc_p + i);
-                muC[i] = vc[0]; muC[i + 1] = vc[1]; muC[i + 2] = vc[2]; muC[i + 3] = vc[3];
-            }
-#pragma unroll
-            for (int nb = 0; nb < NB; ++nb) {
-                float q = 0.0f;
-#pragma unroll
-                for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-                    for (int rr = 0; rr < 4; ++rr)
-                        q = fmaf(xC[nb][mb * 4 + rr] - muC[mb * 4 + rr], acc[nb][mb][rr], q);
-                q = rows4_sum(q);
-                float l2, w = 1.0f;
-                if constexpr (FAM == 0) {
-                    l2 = r.lc2 - q * (0.5f * kLog2e);
-                } else {
-                    l2 = r.lc2 - (0.5f * nupd * kLog2e) * log1pf(q / nu);
-                    w = nupd / (nu + q);
-                }
-                const float mnew = fmaxf(mrun[nb], l2);
-                const float sc = __builtin_amdgcn_exp2f(mrun[nb] - mnew);
-                const float pk = __builtin_amdgcn_exp2f(l2 - mnew);
-                const bool moved = mnew > mrun[nb];
-                srun[nb] = fmaf(srun[nb], sc, pk);
-                mrun[nb] = mnew;
-                if constexpr (GRAD) {
-                    if (__any(moved)) {
-#pragma unroll
-                        for (int i = 0; i < KS; ++i) gacc[nb][i] *= sc;
-                    }
-                    const float pw = pk * w;
-#pragma unroll
-                    for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-                        for (int rr = 0; rr < 4; ++rr)
-                            gacc[nb][mb * 4 + rr] = fmaf(pw, acc[nb][mb][rr], gacc[nb][mb * 4 + rr]);
-                }
-            }
-        };
-        const int K = pd.K;
-        const int kb = SPLIT == 1 ? 0 : (wv * K) / SPLIT, ke = SPLIT == 1 ? K : ((wv + 1) * K) / SPLIT;
-        if constexpr (DP < 64) {
-            // small components: too little work per component to hide its load
-            // latency behind the other wave, so the next one is loaded into a
-            // second register set while this one is contracted (the set is
-            // small at DP <= 32); the prefetch past the end reloads the last
-            // component, which keeps the loop branch-free
-            if (kb < ke) {
-                CompRegs<KS, MB> rb;
-                load(kb, ra);
-                for (int k = kb; k < ke; k += 2) {
-                    load(min(k + 1, ke - 1), rb);
-                    step(k, ra);
-                    if (k + 1 >= ke) break;
-                    load(min(k + 2, ke - 1), ra);
-                    step(k + 1, rb);
-                }
-            }
-        } else {
-            for (int k = kb; k < ke; ++k) {
-                load(k, ra);
-                step(k, ra);
-            }
-        }
-        if constexpr (SPLIT > 1) {
-            // merge: m = max(m0, m_v), s = s0 2^(m0-m) + s_v 2^(m_v-m), the
-            // gradient sums alike, for v = 1, 2, ... in order
-            if (!lead) {
-#pragma unroll
-                for (int nb = 0; nb < NB; ++nb) {
-                    s_pm[wv - 1][nb][lane] = mrun[nb];
-                    s_ps[wv - 1][nb][lane] = srun[nb];
-                    if constexpr (GRAD)
-#pragma unroll
-                        for (int i = 0; i < KS; ++i) s_pg[((wv - 1) * NB + nb) * KS + i][lane] = gacc[nb][i];
-                }
-            }
-            __syncthreads();
-            if (lead) {
-                for (int v = 0; v < SPLIT - 1; ++v) {
-#pragma unroll
-                    for (int nb = 0; nb < NB; ++nb) {
-                        const float mv = s_pm[v][nb][lane];
-                        if (!(mv > -INFINITY)) continue;  // no components in that part
-                        const float mn = fmaxf(mrun[nb], mv);
-                        const float a0 = __builtin_amdgcn_exp2f(mrun[nb] - mn);
-                        const float a1 = __builtin_amdgcn_exp2f(mv - mn);
-                        srun[nb] = fmaf(srun[nb], a0, s_ps[v][nb][lane] * a1);
-                        if constexpr (GRAD)
-#pragma unroll
-                            for (int i = 0; i < KS; ++i)
-                                gacc[nb][i] = fmaf(gacc[nb][i], a0, s_pg[(v * NB + nb) * KS + i][lane] * a1);
-                        mrun[nb] = mn;
-                    }
-                }
-            }
-        }
-        // ---- results to LDS ------------------------------------------------
         // Noisy problems: every value the method sees carries sigma_n z, z the
         // first normal of the NOISE stream at (sample, cycle, step << 16 |
         // sub); the gate value carries sigma_n times the mean of gate_reps
         // normals of the GATE stream.  The gradient stays noise-free.
         const bool noisy = !ext && a.nz_kind >= 0 && pd.noise_sigma > 0.0f;
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-            if (!lead) break;
-            const int pt = nb * 16 + n;
-            float f = (mrun[nb] + __log2f(srun[nb])) * kLn2;
-            if (noisy && g == 0 && s_s[pt] >= 0) {
-                const uint32_t ls = (uint32_t)(s_s[pt] - pd.s0);
-                if (a.nz_kind == 0) {
-                    uint32_t sub = a.nz_base;
-                    if constexpr (CENTER == kTrial) sub += (uint32_t)(r0 + s_c[pt]);
-                    if constexpr (CENTER == kProbe) sub |= (uint32_t)s_c[pt] << 7;
-                    if constexpr (FD) sub += (uint32_t)s_st[pt];
-                    float z[4];
-                    box_muller4(philox(ls, kcyc, (kNoise << 24) | ((uint32_t)a.step << 16) | sub, 0u, pd.key0, pd.key1),
-                                z);
-                    f += pd.noise_sigma * z[0];
-                } else {
-                    float zs = 0.0f;
-                    for (int b = 0; 4 * b < pd.gate_reps; ++b) {
-                        float z[4];
-                        box_muller4(philox(ls, kcyc, kGate << 24, (uint32_t)b, pd.key0, pd.key1), z);
-                        for (int q = 0; q < 4 && 4 * b + q < pd.gate_reps; ++q) zs += z[q];
-                    }
-                    f += pd.noise_sigma * (zs / (float)pd.gate_reps);
-                }
+        auto noise_of = [&](int pt) -> float {
+            const uint32_t ls = (uint32_t)(s_s[pt] - pd.s0);
+            if (a.nz_kind == 0) {
+                uint32_t sub = a.nz_base;
+                if constexpr (CENTER == kTrial) sub += (uint32_t)(r0 + s_c[pt]);
+                if constexpr (CENTER == kProbe) sub |= (uint32_t)s_c[pt] << 7;
+                if constexpr (FD) sub += (uint32_t)s_st[pt];
+                float z[4];
+                box_muller4(philox(ls, kcyc, (kNoise << 24) | ((uint32_t)a.step << 16) | sub, 0u, pd.key0, pd.key1), z);
+                return pd.noise_sigma * z[0];
             }
-            if (g == 0) s_f[pt] = f;
-            if constexpr (GRAD) {
-                const float inv = -1.0f / srun[nb];
+            float zs = 0.0f;
+            for (int b = 0; 4 * b < pd.gate_reps; ++b) {
+                float z[4];
+                box_muller4(philox(ls, kcyc, kGate << 24, (uint32_t)b, pd.key0, pd.key1), z);
+                for (int q = 0; q < 4 && 4 * b + q < pd.gate_reps; ++q) zs += z[q];
+            }
+            return pd.noise_sigma * (zs / (float)pd.gate_reps);
+        };
+        if constexpr (CLOSED) {
+            // ---- closed-form value (and gradient), two lanes per point ------
+            const int pt = lane >> 1, c0 = lane & 1;
+            const float *x = s_pts + pt * LD;
+            float sa, sb;
+            cf_partial(pd.family, d, x, c0, sa, sb);
+            sa += __shfl_xor(sa, 1, kWave);
+            sb += __shfl_xor(sb, 1, kWave);
+            if (s_s[pt] >= 0) {
+                if (c0 == 0) {
+                    float f = cf_value(pd.family, d, sa, sb);
+                    if (noisy) f += noise_of(pt);
+                    s_f[pt] = f;
+                }
+                if constexpr (GRAD)
+                    for (int c = c0; c < d; c += 2) s_g[pt * LD + c] = cf_grad(pd.family, d, x, c, sa, sb);
+            }
+            __syncthreads();
+        } else {
+            // ---- operand registers ---------------------------------------------
+            float xB[NB][KS], xC[NB][KS];
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                const float *row = s_pts + (nb * 16 + n) * LD;
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks) xB[nb][ks] = row[4 * ks + g];
 #pragma unroll
                 for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) s_g[pt * LD + 16 * mb + 4 * g + r] = gacc[nb][mb * 4 + r] * inv;
+                    for (int r = 0; r < 4; ++r) xC[nb][mb * 4 + r] = row[16 * mb + 4 * g + r];
             }
+            float mrun[NB], srun[NB];
+            float gacc[NB][GRAD ? KS : 1];
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                mrun[nb] = -INFINITY;
+                srun[nb] = 0.0f;
+                if constexpr (GRAD)
+#pragma unroll
+                    for (int i = 0; i < KS; ++i) gacc[nb][i] = 0.0f;
+            }
+            // ---- stream the components -----------------------------------------
+            // Two waves per SIMD: while one waits for a component's operands or
+            // works through the log-sum-exp epilogue on the VALU, the other keeps
+            // the matrix core busy; a wave raises its priority for the duration of
+            // its MFMA block so the arbiter keeps the matrix core fed.  Operands
+            // come through global-address-space pointers: flat loads would also
+            // count against the LDS counter, and the cross-lane reductions of the
+            // epilogue would then wait for them.
+            const gfloat *Pfrag = as_global(pd.Pfrag), *muBk = as_global(pd.muB), *muCk = as_global(pd.muC),
+                         *logc2 = as_global(pd.logc2);
+            const float nu = pd.nu, nupd = pd.nu_plus_d;
+            CompRegs<KS, MB> ra;
+            auto load = [&](int k, CompRegs<KS, MB> &r) {
+                const gfloat *pf = Pfrag + (size_t)k * KS * kWave * MB + lane * MB;
+                const gfloat *mb_p = muBk + ((size_t)k * 4 + g) * KS;
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks) load_frag<MB>(pf + (size_t)ks * kWave * MB, r.pa[ks]);
+#pragma unroll
+                for (int i = 0; i < KS; i += 4) {
+                    const f32x4 vb = *reinterpret_cast<const gf32x4 *>(mb_p + i);
+                    r.muB[i] = vb[0]; r.muB[i + 1] = vb[1]; r.muB[i + 2] = vb[2]; r.muB[i + 3] = vb[3];
+                }
+                r.lc2 = logc2[k];
+            };
+            auto step = [&](int k, const CompRegs<KS, MB> &r) {
+                f32x4 acc[NB][MB];
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+                    for (int mb = 0; mb < MB; ++mb) acc[nb][mb] = f32x4{0.f, 0.f, 0.f, 0.f};
+                __builtin_amdgcn_s_setprio(1);
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks) {
+#pragma unroll
+                    for (int nb = 0; nb < NB; ++nb) {
+                        const float b = xB[nb][ks] - r.muB[ks];
+#pragma unroll
+                        for (int mb = 0; mb < MB; ++mb)
+                            acc[nb][mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(r.pa[ks][mb], b, acc[nb][mb], 0, 0, 0);
+                    }
+                }
+                __builtin_amdgcn_s_setprio(0);
+                // centre coordinates in accumulator-lane order, only needed now
+                float muC[KS];
+                const gfloat *mc_p = muCk + ((size_t)k * 4 + g) * KS;
+#pragma unroll
+                for (int i = 0; i < KS; i += 4) {
+                    const f32x4 vc = *reinterpret_cast<const gf32x4 *>(mc_p + i);
+                    muC[i] = vc[0]; muC[i + 1] = vc[1]; muC[i + 2] = vc[2]; muC[i + 3] = vc[3];
+                }
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) {
+                    float q = 0.0f;
+#pragma unroll
+                    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                        for (int rr = 0; rr < 4; ++rr)
+                            q = fmaf(xC[nb][mb * 4 + rr] - muC[mb * 4 + rr], acc[nb][mb][rr], q);
+                    q = rows4_sum(q);
+                    float l2, w = 1.0f;
+                    if constexpr (FAM == 0) {
+                        l2 = r.lc2 - q * (0.5f * kLog2e);
+                    } else {
+                        l2 = r.lc2 - (0.5f * nupd * kLog2e) * log1pf(q / nu);
+                        w = nupd / (nu + q);
+                    }
+                    const float mnew = fmaxf(mrun[nb], l2);
+                    const float sc = __builtin_amdgcn_exp2f(mrun[nb] - mnew);
+                    const float pk = __builtin_amdgcn_exp2f(l2 - mnew);
+                    const bool moved = mnew > mrun[nb];
+                    srun[nb] = fmaf(srun[nb], sc, pk);
+                    mrun[nb] = mnew;
+                    if constexpr (GRAD) {
+                        if (__any(moved)) {
+#pragma unroll
+                            for (int i = 0; i < KS; ++i) gacc[nb][i] *= sc;
+                        }
+                        const float pw = pk * w;
+#pragma unroll
+                        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                            for (int rr = 0; rr < 4; ++rr)
+                                gacc[nb][mb * 4 + rr] = fmaf(pw, acc[nb][mb][rr], gacc[nb][mb * 4 + rr]);
+                    }
+                }
+            };
+            const int K = pd.K;
+            const int kb = SPLIT == 1 ? 0 : (wv * K) / SPLIT, ke = SPLIT == 1 ? K : ((wv + 1) * K) / SPLIT;
+            if constexpr (DP < 64) {
+                // small components: too little work per component to hide its load
+                // latency behind the other wave, so the next one is loaded into a
+                // second register set while this one is contracted (the set is
+                // small at DP <= 32); the prefetch past the end reloads the last
+                // component, which keeps the loop branch-free
+                if (kb < ke) {
+                    CompRegs<KS, MB> rb;
+                    load(kb, ra);
+                    for (int k = kb; k < ke; k += 2) {
+                        load(min(k + 1, ke - 1), rb);
+                        step(k, ra);
+                        if (k + 1 >= ke) break;
+                        load(min(k + 2, ke - 1), ra);
+                        step(k + 1, rb);
+                    }
+                }
+            } else {
+                for (int k = kb; k < ke; ++k) {
+                    load(k, ra);
+                    step(k, ra);
+                }
+            }
+            if constexpr (SPLIT > 1) {
+                // merge: m = max(m0, m_v), s = s0 2^(m0-m) + s_v 2^(m_v-m), the
+                // gradient sums alike, for v = 1, 2, ... in order
+                if (!lead) {
+#pragma unroll
+                    for (int nb = 0; nb < NB; ++nb) {
+                        s_pm[wv - 1][nb][lane] = mrun[nb];
+                        s_ps[wv - 1][nb][lane] = srun[nb];
+                        if constexpr (GRAD)
+#pragma unroll
+                            for (int i = 0; i < KS; ++i) s_pg[((wv - 1) * NB + nb) * KS + i][lane] = gacc[nb][i];
+                    }
+                }
+                __syncthreads();
+                if (lead) {
+                    for (int v = 0; v < SPLIT - 1; ++v) {
+#pragma unroll
+                        for (int nb = 0; nb < NB; ++nb) {
+                            const float mv = s_pm[v][nb][lane];
+                            if (!(mv > -INFINITY)) continue;  // no components in that part
+                            const float mn = fmaxf(mrun[nb], mv);
+                            const float a0 = __builtin_amdgcn_exp2f(mrun[nb] - mn);
+                            const float a1 = __builtin_amdgcn_exp2f(mv - mn);
+                            srun[nb] = fmaf(srun[nb], a0, s_ps[v][nb][lane] * a1);
+                            if constexpr (GRAD)
+#pragma unroll
+                                for (int i = 0; i < KS; ++i)
+                                    gacc[nb][i] = fmaf(gacc[nb][i], a0, s_pg[(v * NB + nb) * KS + i][lane] * a1);
+                            mrun[nb] = mn;
+                        }
+                    }
+                }
+            }
+            // ---- results to LDS --------------------------------------------
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                if (!lead) break;
+                const int pt = nb * 16 + n;
+                float f = (mrun[nb] + __log2f(srun[nb])) * kLn2;
+                if (noisy && g == 0 && s_s[pt] >= 0) f += noise_of(pt);
+                if (g == 0) s_f[pt] = f;
+                if constexpr (GRAD) {
+                    const float inv = -1.0f / srun[nb];
+#pragma unroll
+                    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) s_g[pt * LD + 16 * mb + 4 * g + r] = gacc[nb][mb * 4 + r] * inv;
+                }
+            }
+            __syncthreads();
         }
-        __syncthreads();
         // ---- epilogues -----------------------------------------------------
         const int os = a.out_stride;
         if constexpr (CENTER == kDirect && !FD) {
@@ -564,7 +697,7 @@ static hipError_t dispatch_modes(const EvalArgs &a, int center, bool fd, bool gr
     const dim3 block(kWave);
 #define CHISAO_GO(C, G, F) hipLaunchKernelGGL((eval_kernel<DP, FAM, G, C, F, 1>), grid, block, 0, st, a)
 #define CHISAO_GO_SPLIT(C, G, F)                                                                       \
-    hipLaunchKernelGGL((eval_kernel<DP, FAM, G, C, F, trial_split<DP>()>), grid, dim3(kWave * trial_split<DP>()), 0, \
+    hipLaunchKernelGGL((eval_kernel<DP, FAM, G, C, F, trial_split<DP, FAM>()>), grid, dim3(kWave * trial_split<DP, FAM>()), 0, \
                        st, a)
     if (center == kDirect) {
         if (fd) CHISAO_GO(kDirect, false, true);
@@ -589,15 +722,20 @@ hipError_t launch_eval(const EvalArgs &a, int DP, int family, int center, bool f
     long g = a.max_tiles < cap ? a.max_tiles : cap;
     if (a.order == 1) g = (g + 7) / 8 * 8;  // whole rounds over the XCDs
     const dim3 grid((unsigned)g);
+    // the closed forms share one instantiation per padded dimension and
+    // select the function per problem
+    const int fam = family >= kFamClosed ? kFamClosed : family;
+#define CHISAO_FAMS(DPV)                                                                  \
+    fam == 0   ? dispatch_modes<DPV, 0>(a, center, fd, grad, grid, st)                   \
+    : fam == 1 ? dispatch_modes<DPV, 1>(a, center, fd, grad, grid, st)                   \
+               : dispatch_modes<DPV, kFamClosed>(a, center, fd, grad, grid, st)
     switch (DP) {
-        case 16: return family ? dispatch_modes<16, 1>(a, center, fd, grad, grid, st)
-                               : dispatch_modes<16, 0>(a, center, fd, grad, grid, st);
-        case 32: return family ? dispatch_modes<32, 1>(a, center, fd, grad, grid, st)
-                               : dispatch_modes<32, 0>(a, center, fd, grad, grid, st);
-        case 64: return family ? dispatch_modes<64, 1>(a, center, fd, grad, grid, st)
-                               : dispatch_modes<64, 0>(a, center, fd, grad, grid, st);
+        case 16: return CHISAO_FAMS(16);
+        case 32: return CHISAO_FAMS(32);
+        case 64: return CHISAO_FAMS(64);
         default: return hipErrorInvalidValue;
     }
+#undef CHISAO_FAMS
 }
 
 // ---------------------------------------------------------------------------

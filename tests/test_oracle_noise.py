@@ -18,9 +18,11 @@ def _noisy_problem(family=W.GAUSS):
 
 
 def _run(prob, N=20000, **kw):
-    cfg = W.RunConfig(N=N, n_conv=0, M=8, eps_grad=1e-3, seed=9, **kw)
+    cfg = W.RunConfig(N=N, n_conv=1, M=8, eps_grad=1e-3, seed=9, **kw)
     x0 = W.uniform_population(5, N, prob.lo, prob.hi)
-    return O.OracleRun(prob, cfg, x0), cfg, x0
+    run = O.OracleRun(prob, cfg, x0)
+    run.cc.n_conv = 0  # Phase 1 reduced to its starting evaluation (value and gradient at x0)
+    return run, cfg, x0
 
 
 def _assert_standard_normal(z, var=1.0):

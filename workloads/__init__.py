@@ -1,33 +1,56 @@
 """Seeded synthetic inputs shared by the oracle tests, the GPU tests and the benchmark.
 
-This package only draws problem instances and starting populations.  It holds
-none of the optimizer's arithmetic: no objective evaluation, no gradient, no
-step of the oscillation cycle.
+This package only draws problem instances and starting populations and states
+the closed-form functions' domains.  It holds none of the optimizer's
+arithmetic: no objective evaluation, no gradient, no step of the oscillation
+cycle.
 """
 from .gen import (
+    ACKLEY,
+    BUKIN6,
+    CLOSED_FORMS,
     GAUSS,
+    MICHALEWICZ,
+    RASTRIGIN,
+    SCHWEFEL,
     STUDENT_T,
+    STYBLINSKI_TANG,
+    TRID,
     Problem,
     RunConfig,
+    closed_form_box,
+    closed_form_problem,
     config1,
     config2,
     config3,
     config4,
     config5,
     mixture_problem,
+    two_peak_problem,
     uniform_population,
 )
 
 __all__ = [
+    "ACKLEY",
+    "BUKIN6",
+    "CLOSED_FORMS",
     "GAUSS",
+    "MICHALEWICZ",
+    "RASTRIGIN",
+    "SCHWEFEL",
     "STUDENT_T",
+    "STYBLINSKI_TANG",
+    "TRID",
     "Problem",
     "RunConfig",
+    "closed_form_box",
+    "closed_form_problem",
     "config1",
     "config2",
     "config3",
     "config4",
     "config5",
     "mixture_problem",
+    "two_peak_problem",
     "uniform_population",
 ]

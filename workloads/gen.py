@@ -19,6 +19,16 @@ import numpy as np
 
 GAUSS = 0
 STUDENT_T = 1
+# closed-form test functions (Appendix D)
+RASTRIGIN = 2
+ACKLEY = 3
+SCHWEFEL = 4
+STYBLINSKI_TANG = 5
+MICHALEWICZ = 6
+TRID = 7
+BUKIN6 = 8
+CLOSED_FORMS = {"rastrigin": RASTRIGIN, "ackley": ACKLEY, "schwefel": SCHWEFEL,
+                "styblinski_tang": STYBLINSKI_TANG, "michalewicz": MICHALEWICZ, "trid": TRID, "bukin6": BUKIN6}
 
 
 @dataclass
@@ -130,6 +140,51 @@ def mixture_problem(
     # symmetric array); make sure nothing upstream broke that.
     assert np.array_equal(prob.prec, np.transpose(prob.prec, (0, 2, 1)))
     return prob
+
+
+def closed_form_box(family: int, d: int):
+    """The search domain Appendix D gives for each closed-form function."""
+    if family == RASTRIGIN:
+        lo, hi = np.full(d, -5.12), np.full(d, 5.12)
+    elif family == ACKLEY:
+        lo, hi = np.full(d, -32.768), np.full(d, 32.768)
+    elif family == SCHWEFEL:
+        lo, hi = np.full(d, -500.0), np.full(d, 500.0)
+    elif family == STYBLINSKI_TANG:
+        lo, hi = np.full(d, -5.0), np.full(d, 5.0)
+    elif family == MICHALEWICZ:
+        lo, hi = np.zeros(d), np.full(d, np.pi)
+    elif family == TRID:
+        lo, hi = np.full(d, -float(d * d)), np.full(d, float(d * d))
+    elif family == BUKIN6:
+        if d != 2:
+            raise ValueError("Bukin N.6 is two-dimensional")
+        lo, hi = np.array([-15.0, -3.0]), np.array([-5.0, 3.0])
+    else:
+        raise ValueError(f"not a closed-form family: {family}")
+    return lo.astype(np.float32), hi.astype(np.float32)
+
+
+def closed_form_problem(name_or_family, d: int, noise_sigma: float = 0.0) -> Problem:
+    """One of the closed-form test functions on its Appendix D domain."""
+    fam = CLOSED_FORMS[name_or_family] if isinstance(name_or_family, str) else int(name_or_family)
+    lo, hi = closed_form_box(fam, d)
+    empty = np.zeros(0, np.float32)
+    return Problem(family=fam, d=d, K=0, log_w=empty, mu=empty.reshape(0, d), prec=empty.reshape(0, d, d),
+                   lo=lo, hi=hi, noise_sigma=float(noise_sigma))
+
+
+def two_peak_problem(noise_sigma: float, d: int = 6, sep: float = 2.0, box: float = 6.0) -> Problem:
+    """Two equal isotropic unit-variance Gaussians at +-sep e_1 (the noise
+    experiment of Sec. 5.7: d = 6, peaks at +-2 e_1, four standard deviations
+    apart)."""
+    mu = np.zeros((2, d))
+    mu[0, 0], mu[1, 0] = sep, -sep
+    prec = np.broadcast_to(np.eye(d), (2, d, d)).copy()
+    return Problem(family=GAUSS, d=d, K=2, log_w=np.log(np.full(2, 0.5)).astype(np.float32),
+                   mu=mu.astype(np.float32), prec=prec.astype(np.float32),
+                   lo=np.full(d, -box, np.float32), hi=np.full(d, box, np.float32),
+                   noise_sigma=float(noise_sigma), lam=np.ones((2, d)))
 
 
 def uniform_population(seed: int, N: int, lo: np.ndarray, hi: np.ndarray) -> np.ndarray:
