@@ -79,7 +79,7 @@ typedef struct {
 /* Schedule and hyperparameters (Sec. 3.6, Table 1).  A value <= 0 in a field
  * marked "auto" selects the rule named next to it. */
 typedef struct {
-    int32_t N;          /* population size, >= 1 */
+    int32_t N;          /* population size, 1..2^30 */
     int32_t m;          /* L-BFGS memory, 1..32 */
     int32_t n_osc;      /* oscillation cycles */
     int32_t n_conv;     /* L-BFGS iterations per cycle; auto: max(10, ceil(3 log2 d)) */

@@ -170,7 +170,7 @@ static int validate(const chisao_problem *p, const chisao_config *c, int idx) {
                     return fail(CHISAO_E_INVAL, "problem %d: precision matrix %d not symmetric", idx, k);
             }
     }
-    if (c->N < 1) return fail(CHISAO_E_INVAL, "problem %d: N must be >= 1", idx);
+    if (c->N < 1 || c->N > (1 << 30)) return fail(CHISAO_E_INVAL, "problem %d: N must be in 1..2^30", idx);
     if (c->m < 1 || c->m > 32) return fail(CHISAO_E_INVAL, "problem %d: m must be in 1..32", idx);
     if (c->n_osc < 1) return fail(CHISAO_E_INVAL, "problem %d: n_osc must be >= 1", idx);
     if (c->n_anti < 0 || c->n_cloud < 0) return fail(CHISAO_E_INVAL, "problem %d: negative step count", idx);
@@ -347,10 +347,11 @@ extern "C" int chisao_init_batched(chisao_handle *out, int n_problems, const chi
             q.noise_sigma = pr.noise_sigma;
             q.gate_reps = c.gate_reps > 0 ? c.gate_reps : c.M;
             {
-                int n2 = 1;
-                while (n2 < c.N) n2 <<= 1;
-                q.rk0 = (int)rk_total;
-                rk_total += (size_t)n2;
+                int lb = 0;  // about four stuck samples per bucket at most
+                while ((4 << lb) < c.N) ++lb;
+                q.hash_lb = lb;
+                q.hk0 = (int)rk_total;
+                rk_total += ((size_t)1 << lb) + 1;
             }
             h->any_noise |= pr.noise_sigma > 0.0f;
         }
@@ -430,7 +431,9 @@ extern "C" int chisao_init_batched(chisao_handle *out, int n_problems, const chi
         ALLOC(D.cnt, int, N);
         ALLOC(D.lists, int, N * kNumLists);
         ALLOC(D.flag, uint8_t, N);
-        ALLOC(D.rkey, unsigned long long, rk_total);
+        ALLOC(D.hoff, int, rk_total);
+        ALLOC(D.hcur, int, rk_total);
+        ALLOC(D.hcell, int, N);
         ALLOC(D.ctl, Ctl, P);
         ALLOC(D.records, CycleRecord, P * (size_t)D.n_osc);
         ALLOC(D.part, double, P * (size_t)D.n_part_blocks * 129);

@@ -143,7 +143,8 @@ struct ProblemDesc {
     uint32_t key0, key1, phase_mask;
     float noise_sigma;  // additive evaluation noise (0: none)
     int gate_reps;      // noisy evaluations averaged by the quality gate
-    int rk0;            // offset of the problem's sort scratch in Dev::rkey (a power of two >= N long)
+    int hk0;            // offset of the problem's 2^hash_lb + 1 deduplication bucket offsets in Dev::hoff
+    int hash_lb;        // log2 of the deduplication bucket count (a power of two >= N/4)
 };
 
 // ---------------------------------------------------------------------------
@@ -153,8 +154,8 @@ struct ProblemDesc {
 // L_T1 and L_T1B alternate between L-BFGS iterations: one holds the samples
 // that took a step in the previous iteration, the other collects this one's.
 // L_T2 / L_T3: searches still open after the first trial / after trials 1-2.
-// L_RANK: a problem's stuck samples in deduplication rank order.
-enum ListId { L_ACT = 0, L_T1, L_T1B, L_T2, L_T3, L_FD, L_UNF, L_STK, L_RANK, O_SLOTS, O_FREE, O_PEAKS, kNumLists };
+// L_HASH: a problem's stuck samples grouped by deduplication hash bucket.
+enum ListId { L_ACT = 0, L_T1, L_T1B, L_T2, L_T3, L_FD, L_UNF, L_STK, L_HASH, O_SLOTS, O_FREE, O_PEAKS, kNumLists };
 
 struct Ctl {
     int k;  // cycles completed
@@ -203,7 +204,9 @@ struct Dev {
     int *head, *cnt;
     int *lists;              // kNumLists x NT; problem p's list occupies [s0, s0 + N)
     uint8_t *flag;           // [NT] per list position: a producer's verdict, read by the compaction
-    unsigned long long *rkey;  // deduplication sort keys of problems with many stuck samples
+    int *hoff;   // deduplication bucket offsets (exclusive scan of the counts), per problem at hk0
+    int *hcur;   // scatter cursors, same layout
+    int *hcell;  // deduplication hash cell of each stuck sample
     Ctl *ctl;                // [P]
     CycleRecord *records;    // [P][n_osc]
     double *part;            // [P][n_part_blocks][129] reduction partials

@@ -483,114 +483,166 @@ hipError_t launch_stick(const Dev &D, hipStream_t st) {
 // ---------------------------------------------------------------------------
 // Phase 3: sample j is removed when another stuck sample i of its problem
 // lies within eps_dup in the sup-norm and ranks above it (higher f, then
-// lower index).  All stuck samples take part, removed or not.  Candidate
-// first coordinates are staged through LDS; the full row is compared only
-// when the first coordinates are within eps_dup.
+// lower index).  All stuck samples take part, removed or not.
 // ---------------------------------------------------------------------------
-// Deduplication in rank order.  The stuck samples of a problem are sorted by
-// (f descending, index ascending), the strict order of the removal rule; then
-// j is removed iff some sample ranked before it lies within eps_dup.  The
-// decision does not depend on the order in which earlier ranks are checked,
-// so each sample first checks its nearest earlier ranks: converged copies of
-// one mode have nearly equal values and sit next to each other in rank
-// order, so almost every sample is settled there.  The few that are not (the
-// best sample of each cluster, samples of loose clusters) then scan all
-// earlier ranks cooperatively, 256 ranks at a time through LDS.
-constexpr int kRankCap = 8192;  // sorted in LDS up to this many stuck samples, in global memory above
-constexpr int kRankBlock = 1024;
-constexpr int kNearRanks = 8;
-
-__device__ __forceinline__ unsigned long long rank_key(float f, int s) {
-    const uint32_t b = __float_as_uint(f);
-    const uint32_t up = (b & 0x80000000u) ? ~b : (b | 0x80000000u);  // ascending with f
-    return ((unsigned long long)(~up) << 32) | (uint32_t)s;            // f descending, then index
+// Deduplication through an L-infinity spatial hash (the hashing of
+// Appendix A): j is removed iff some stuck sample i of its problem lies
+// within eps_dup and ranks above it, (f_i, -i) > (f_j, -j).  The decision
+// only asks whether such an i exists, so any candidate order gives the same
+// answer; candidates come from j's own and the two adjacent hash cells, which
+// makes the phase O(N) in the expected case instead of O(N^2).
+//
+// The hash is one fixed projection p(x) = sum_c v_c x_c with weights
+// v_c = 1/2 + frac((c + 1) phi) (a Weyl sequence: no two coordinates weigh
+// alike, so the distinct maxima of lattice-like landscapes, which share
+// coordinate values, still land in different cells), cut into cells of width
+// 2 eps |v|_1 (1 + 2^-20).  Two samples within eps in the sup-norm differ in
+// p by less than eps |v|_1 (FP32 coordinate differences round by at most one
+// ulp, inside the margin), so they lie in the same or adjacent cells.  p is
+// formed in FP64: its rounding (~d 2^-53 |v|_1 max|x|) is far inside the
+// margin.  Hashing every coordinate on its own grid instead would need 3^d
+// neighbouring cells.
+//
+// Cells go to B = 2^hash_lb >= N/4 buckets by multiplicative hashing; a
+// counting sort (count, exclusive scan, scatter) groups a problem's stuck
+// samples by bucket in its L_HASH list.  Buckets may hold several cells; a
+// candidate is compared only when its cell is the one being visited.
+__device__ __forceinline__ double hash_weight(int c) {
+    const double w = (double)(c + 1) * 0.61803398874989484820;
+    return 0.5 + (w - floor(w));
 }
 
-// Bitonic sort (ascending) of key[0, n2), n2 a power of two, by one workgroup.
-__device__ void bitonic_sort(unsigned long long *key, int n2) {
-    for (int k = 2; k <= n2; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int t = threadIdx.x; t < n2; t += blockDim.x) {
-                const int u = t ^ j;
-                if (u > t) {
-                    const unsigned long long a = key[t], b = key[u];
-                    if ((a > b) == ((t & k) == 0)) {
-                        key[t] = b;
-                        key[u] = a;
-                    }
-                }
-            }
-            __syncthreads();
-        }
-    }
+// cell of row x; clamping to the int range keeps adjacent cells adjacent
+__device__ __forceinline__ int hash_cell(const float *x, int d, double inv_width) {
+    double p = 0.0;
+    for (int c = 0; c < d; ++c) p += hash_weight(c) * (double)x[c];
+    const double q = floor(p * inv_width);
+    return (int)fmin(fmax(q, -2147483647.0), 2147483646.0);
 }
 
-__global__ __launch_bounds__(kRankBlock) void dedup_rank_kernel(Dev D) {
-    __shared__ unsigned long long lkey[kRankCap];
-    const int p = blockIdx.x;
+__device__ __forceinline__ double hash_inv_width(int d, float eps) {
+    double v1 = 0.0;
+    for (int c = 0; c < d; ++c) v1 += hash_weight(c);
+    return 1.0 / (2.0 * (double)eps * v1 * (1.0 + 0x1p-20));
+}
+
+__device__ __forceinline__ uint32_t hash_bucket(int cell, int lb) {
+    return lb == 0 ? 0u : ((uint32_t)cell * 0x9E3779B1u) >> (32 - lb);
+}
+
+__global__ void dedup_clear_kernel(Dev D) {
+    const int p = blockIdx.y;
     const ProblemDesc &pd = D.pd[p];
-    if (!((pd.phase_mask >> 3) & 1)) return;
-    const int ns = D.ctl[p].count[L_STK];
-    if (ns == 0) return;
-    const int *lst = list_ptr(D, L_STK, pd.s0);
-    const float *Fv = gate_values(D, pd);
-    int n2 = 1;
-    while (n2 < ns) n2 <<= 1;
-    // above kRankCap the keys live in the problem's global scratch (n2 <= its length)
-    unsigned long long *key = ns <= kRankCap ? lkey : D.rkey + pd.rk0;
-    for (int t = threadIdx.x; t < n2; t += blockDim.x) key[t] = t < ns ? rank_key(Fv[lst[t]], lst[t]) : ~0ull;
-    __syncthreads();
-    bitonic_sort(key, n2);
-    int *out = list_ptr(D, L_RANK, pd.s0);
-    for (int t = threadIdx.x; t < ns; t += blockDim.x) out[t] = (int)(key[t] & 0xFFFFFFFFull);
+    int *cnt = D.hoff + pd.hk0;
+    const int nb = (1 << pd.hash_lb) + 1;
+    for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < nb; b += gridDim.x * blockDim.x) cnt[b] = 0;
 }
 
-__global__ __launch_bounds__(kBlock) void dedup_scan_kernel(Dev D) {
-    __shared__ int t_i[kBlock];
-    __shared__ float t_x0[kBlock];
+__global__ void dedup_count_kernel(Dev D) {
     const int p = blockIdx.y;
     const ProblemDesc &pd = D.pd[p];
     if (!((pd.phase_mask >> 3) & 1)) return;
     const int ns = D.ctl[p].count[L_STK];
-    const int *rk = list_ptr(D, L_RANK, pd.s0);
-    const int d = pd.d, DS = D.DS;
-    const float eps = pd.eps_dup;
-    auto near = [&](int i, int j, float xj0) {
-        if (!(fabsf(D.X[(size_t)i * DS] - xj0) < eps)) return false;
-        for (int c = 1; c < d; ++c)
-            if (!(fabsf(D.X[(size_t)i * DS + c] - D.X[(size_t)j * DS + c]) < eps)) return false;
-        return true;
-    };
-    for (int r0 = blockIdx.x * kBlock; r0 < ns; r0 += gridDim.x * kBlock) {
-        const int r = r0 + threadIdx.x;
-        const int j = r < ns ? rk[r] : -1;
-        const float xj0 = j >= 0 ? D.X[(size_t)j * DS] : 0.0f;
-        bool rem = false;
-        // nearest earlier ranks first
-        for (int q = r - 1; j >= 0 && q >= 0 && q >= r - kNearRanks && !rem; --q) rem = near(rk[q], j, xj0);
-        bool open = j >= 0 && !rem && r > kNearRanks;
-        // the rest cooperatively, over ranks [0, r - kNearRanks)
-        for (int tb = 0; __syncthreads_or(open) && tb < r0 + kBlock; tb += kBlock) {
-            const int q = tb + threadIdx.x;
-            if (q < ns) {
-                t_i[threadIdx.x] = rk[q];
-                t_x0[threadIdx.x] = D.X[(size_t)rk[q] * DS];
-            }
+    const int *lst = list_ptr(D, L_STK, pd.s0);
+    const double inv_w = hash_inv_width(pd.d, pd.eps_dup);
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < ns; t += gridDim.x * blockDim.x) {
+        const int s = lst[t];
+        const int cell = hash_cell(D.X + (size_t)s * D.DS, pd.d, inv_w);
+        D.hcell[s] = cell;
+        atomicAdd(&D.hoff[pd.hk0 + hash_bucket(cell, pd.hash_lb)], 1);
+    }
+}
+
+// exclusive scan of the bucket counts, one workgroup per problem; the
+// scatter cursors start as a copy of the offsets
+constexpr int kScanBlock = 1024;
+__global__ __launch_bounds__(kScanBlock) void dedup_offsets_kernel(Dev D) {
+    __shared__ int part[kScanBlock];
+    const int p = blockIdx.x;
+    const ProblemDesc &pd = D.pd[p];
+    if (!((pd.phase_mask >> 3) & 1)) return;
+    int *off = D.hoff + pd.hk0, *cur = D.hcur + pd.hk0;
+    const int nb = 1 << pd.hash_lb;
+    int carry = 0;
+    for (int b0 = 0; b0 < nb; b0 += kScanBlock) {
+        const int b = b0 + threadIdx.x;
+        const int v = b < nb ? off[b] : 0;
+        part[threadIdx.x] = v;
+        __syncthreads();
+        for (int o = 1; o < kScanBlock; o <<= 1) {
+            const int add = threadIdx.x >= o ? part[threadIdx.x - o] : 0;
             __syncthreads();
-            if (open) {
-                const int lim = min(kBlock, r - kNearRanks - tb);
-                for (int u = 0; u < lim; ++u) {
-                    if (!(fabsf(t_x0[u] - xj0) < eps)) continue;
-                    if (near(t_i[u], j, xj0)) {
-                        rem = true;
-                        break;
-                    }
-                }
-                if (rem || tb + kBlock >= r - kNearRanks) open = false;
-            }
+            part[threadIdx.x] += add;
             __syncthreads();
         }
-        if (rem) D.removed[j] = 1;
+        const int excl = carry + part[threadIdx.x] - v;
+        if (b < nb) {
+            off[b] = excl;
+            cur[b] = excl;
+        }
+        carry += part[kScanBlock - 1];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) off[nb] = carry;
+}
+
+__global__ void dedup_scatter_kernel(Dev D) {
+    const int p = blockIdx.y;
+    const ProblemDesc &pd = D.pd[p];
+    if (!((pd.phase_mask >> 3) & 1)) return;
+    const int ns = D.ctl[p].count[L_STK];
+    const int *lst = list_ptr(D, L_STK, pd.s0);
+    int *ent = list_ptr(D, L_HASH, pd.s0);
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < ns; t += gridDim.x * blockDim.x) {
+        const int s = lst[t];
+        const int pos = atomicAdd(&D.hcur[pd.hk0 + hash_bucket(D.hcell[s], pd.hash_lb)], 1);
+        ent[pos] = s;
+    }
+}
+
+// One wave per stuck sample: the lanes go through the candidates of a bucket
+// 64 at a time, so the few samples whose buckets hold a whole cluster of
+// converged copies (the best copy of a cluster finds no better one and
+// checks them all) do not serialise the phase.
+__global__ __launch_bounds__(kBlock) void dedup_scan_kernel(Dev D) {
+    const int p = blockIdx.y;
+    const ProblemDesc &pd = D.pd[p];
+    if (!((pd.phase_mask >> 3) & 1)) return;
+    const int ns = D.ctl[p].count[L_STK];
+    const int *lst = list_ptr(D, L_STK, pd.s0);
+    const int *ent = list_ptr(D, L_HASH, pd.s0);
+    const int *off = D.hoff + pd.hk0;
+    const float *Fv = gate_values(D, pd);
+    const int d = pd.d, DS = D.DS;
+    const float eps = pd.eps_dup;
+    const int lane = threadIdx.x % kWave;
+    const int wpb = blockDim.x / kWave;
+    for (int t = blockIdx.x * wpb + threadIdx.x / kWave; t < ns; t += gridDim.x * wpb) {
+        const int j = lst[t];
+        const int cj = D.hcell[j];
+        const float fj = Fv[j];
+        const float *xj = D.X + (size_t)j * DS;
+        bool rem = false;
+        for (int dc = -1; dc <= 1 && !rem; ++dc) {
+            const int c = cj + dc;
+            const uint32_t b = hash_bucket(c, pd.hash_lb);
+            const int q1 = off[b + 1];
+            for (int q0 = off[b]; q0 < q1 && !rem; q0 += kWave) {
+                const int q = q0 + lane;
+                bool hit = false;
+                if (q < q1) {
+                    const int i = ent[q];
+                    const float fi = Fv[i];
+                    if (D.hcell[i] == c && i != j && (fi > fj || (fi == fj && i < j))) {
+                        const float *xi = D.X + (size_t)i * DS;
+                        hit = true;
+                        for (int k = 0; k < d && hit; ++k) hit = fabsf(xi[k] - xj[k]) < eps;
+                    }
+                }
+                rem = __any(hit);
+            }
+        }
+        if (rem && lane == 0) D.removed[j] = 1;
     }
 }
 
@@ -635,8 +687,13 @@ __global__ void gr_book_kernel(Dev D) {
 hipError_t launch_dedup(const Dev &D, hipStream_t st) {
     hipLaunchKernelGGL(dedup_reset_kernel, dim3(grid_for(D.P, 64)), dim3(64), 0, st, D);
     hipLaunchKernelGGL(clear_removed_kernel, dim3(grid_for(D.NT, kBlock, 1024)), dim3(kBlock), 0, st, D);
-    hipLaunchKernelGGL(dedup_rank_kernel, dim3(D.P), dim3(kRankBlock), 0, st, D);
-    hipLaunchKernelGGL(dedup_scan_kernel, dim3(grid_for(D.NT / D.P + 1, kBlock, 256), D.P), dim3(kBlock), 0, st, D);
+    const dim3 per_sample(grid_for(D.NT / D.P + 1, kBlock, 256), D.P);
+    const dim3 per_wave(grid_for(D.NT / D.P + 1, kBlock / kWave, 4096), D.P);
+    hipLaunchKernelGGL(dedup_clear_kernel, dim3(grid_for(D.NT / D.P + 2, kBlock, 256), D.P), dim3(kBlock), 0, st, D);
+    hipLaunchKernelGGL(dedup_count_kernel, per_sample, dim3(kBlock), 0, st, D);
+    hipLaunchKernelGGL(dedup_offsets_kernel, dim3(D.P), dim3(kScanBlock), 0, st, D);
+    hipLaunchKernelGGL(dedup_scatter_kernel, per_sample, dim3(kBlock), 0, st, D);
+    hipLaunchKernelGGL(dedup_scan_kernel, per_wave, dim3(kBlock), 0, st, D);
     hipLaunchKernelGGL(dedup_finalize_kernel, dim3(grid_for(D.NT, kBlock, 1024)), dim3(kBlock), 0, st, D);
     hipLaunchKernelGGL(gr_book_kernel, dim3(grid_for(D.P, 64)), dim3(64), 0, st, D);
     return hipGetLastError();

@@ -289,3 +289,72 @@ def test_full_cycle_parity_with_replay():
             np.testing.assert_array_equal(run.stuck, s1["stuck"])
             r = _rows_close(s1["X"], run.X, 1e-4, f"X after cycle {s1['k']}")
             print(f"  X relative error max {r.max():.2e}")
+
+
+@pytest.mark.parametrize("N,eps_dup", [(20000, 1e-3), (6000, 0.7)])
+def test_dedup_lattice_of_maxima_matches_oracle(N, eps_dup):
+    """Styblinski-Tang in d=16 has 2^16 local maxima on a lattice whose
+    points share coordinate values, with the quality gate opened
+    (log_delta = -1e30) so that every stationary sample sticks: thousands of
+    distinct maxima plus duplicates, the case the spatial hash is for.  With
+    eps_dup = 0.7 converged copies and near-converged samples chain across
+    hash cells.  Decisions against the oracle's all-pairs rule."""
+    prob = W.closed_form_problem("styblinski_tang", 16)
+    cfg = W.RunConfig(N=N, m=8, n_osc=3, n_conv=30, eps_grad=1e-2, eps_dup=eps_dup, log_delta=-1e30,
+                      grad_mode=1, seed=2)
+    x0 = W.uniform_population(2, N, prob.lo, prob.hi)
+    with _gpu(prob, cfg, x0) as opt:
+        opt.run_phases(1 << 1)
+        g1 = opt.get_state()
+        opt.run_phases((1 << 2) | (1 << 3))
+        g3 = opt.get_state()
+    n_stuck = int(g3["stuck_pre"].sum())
+    print(f"\nN={N} eps_dup={eps_dup}: stuck {n_stuck}, removed {int(g3['removed'].sum())}, "
+          f"modes {int(g3['stuck'].sum())}")
+    assert n_stuck > 0.5 * N and g3["removed"].sum() > 0
+    run = _oracle_from(prob, cfg, g1)
+    r2 = run.phase_stick(stuck_in=g3["stuck_pre"], **REPLAY)
+    r3 = run.phase_dedup(removed_in=g3["removed"], **REPLAY)
+    assert r2.n_hard == 0 and r3.n_hard == 0, (r2, r3)
+    np.testing.assert_array_equal(run.stuck, g3["stuck"])
+
+
+def test_dedup_pairs_across_hash_cells_match_oracle():
+    """Designed positions: 1500 pairs whose members lie 0.5-0.9 eps_dup apart
+    in the sup-norm (must be merged), 500 pairs 1.1-1.5 eps_dup apart (must
+    not be), random directions, so that a large share of the merged pairs
+    straddle a boundary of the deduplication hash's cells.  The phase-1 state
+    of a unimodal problem with the stick test opened (every sample sticks)
+    supplies values and gradients; the positions are then replaced.  Exact
+    agreement with the oracle's all-pairs rule."""
+    from paper_2606_26164_amd.api import Optimizer
+
+    d, eps = 8, 1e-3
+    prob = W.mixture_problem(3, d, 1, 2.0, isotropic_var=4.0)
+    N = 4000
+    cfg = W.RunConfig(N=N, m=6, n_osc=3, n_conv=10, eps_grad=1e9, eps_dup=eps, log_delta=-1e30, grad_mode=1,
+                      seed=3)
+    rng = np.random.default_rng(8)
+    base = rng.uniform(-2.0, 2.0, size=(2000, d))
+    sign = rng.choice([-1.0, 1.0], size=(2000, d))
+    mag = np.where(np.arange(2000)[:, None] < 1500, rng.uniform(0.5, 0.9, size=(2000, d)),
+                   rng.uniform(1.1, 1.5, size=(2000, d)))
+    # far pairs: one coordinate beyond eps, the others anywhere inside
+    far = np.arange(2000) >= 1500
+    mag[far, 1:] = rng.uniform(0.0, 0.9, size=(far.sum(), d - 1))
+    X = np.concatenate([base, base + sign * mag * eps]).astype(np.float32)
+    x0 = W.uniform_population(3, N, prob.lo, prob.hi)
+    with Optimizer(prob, cfg, x0) as opt:
+        opt.run_phases(1 << 1)
+        opt.set_state(X=X)
+        g1 = opt.get_state()
+        opt.run_phases((1 << 2) | (1 << 3))
+        g3 = opt.get_state()
+    assert g3["stuck_pre"].all()
+    removed = g3["removed"].astype(bool)
+    pair_removed = removed[:2000] | removed[2000:]
+    assert pair_removed[:1500].all() and not pair_removed[1500:].any()
+    run = _oracle_from(prob, cfg, g1)
+    run.phase_stick()
+    run.phase_dedup()
+    np.testing.assert_array_equal(run.removed.astype(bool), removed)
