@@ -109,6 +109,21 @@ typedef struct {
 
 #define CHISAO_FLAG_NO_GRAPH 1u    /* enqueue every cycle's kernels one by one instead of replaying a captured hipGraph */
 #define CHISAO_FLAG_NO_AUTOTUNE 2u /* keep the default evaluation schedule (linear tile order, 8192 workgroups) */
+/* Read per problem: when the problem's starting population is not given, draw
+ * it on rays through the centre of the box from its vertices, edge midpoints
+ * and face centres (the structured ray seeding of Sec. 5.3) instead of
+ * uniformly.  Sample i takes, from Philox counter (i, 0, 0 << 24 | 1, b):
+ * block 0 gives the anchor kind (vertex, edge midpoint, face centre; integer
+ * below 3 of the first word), the coordinate e that is free (edge) or fixed
+ * (face) (integer below d of the second word) and the ray position t (uniform
+ * of the third word); block 1 gives one bit per coordinate (bit c of the
+ * first word, c < 32, of the second word, c >= 32) choosing the bound hi (1)
+ * or lo (0).  The anchor has every coordinate at its chosen bound (vertex),
+ * all but e (edge midpoint, e at the middle), or only e (face centre, the
+ * others at the middle); the sample lies at t along the segment from the
+ * anchor through the centre to the opposite anchor: a bound coordinate is
+ * lo + t (hi - lo) or hi - t (hi - lo), a middle one lo + (hi - lo) / 2. */
+#define CHISAO_FLAG_RAY_SEEDING 4u
 
 /* Per-cycle statistics (host struct). */
 typedef struct {

@@ -71,6 +71,7 @@ typedef struct {
     uint32_t phase_mask; /* bit p enables phase p (3..6); phases 1, 2 always run */
     uint64_t seed;
     uint32_t problem_id;
+    uint32_t flags;      /* bit 2: structured ray seeding of the starting population */
 } orc_config;
 
 typedef struct {
@@ -1322,9 +1323,46 @@ int orc_cycle(const orc_problem *P, const double *logc, const orc_config *C, orc
 }
 
 /* Initial population, uniform in the box from the INIT stream. */
+/* Starting population (INIT stream, counter = sample index).  Uniform in the
+ * box, or, with flag bit 2, the structured ray seeding the paper names for
+ * its carry_tiger runs (Sec. 5.3), which it describes only as rays from the
+ * domain's vertices, edges and faces.  Reading: sample i picks an anchor on
+ * the boundary -- a vertex, an edge midpoint or a face centre, each with
+ * probability 1/3 -- and lies uniformly on the segment from that anchor
+ * through the box centre to the opposite anchor.  Draws: counter
+ * (i, 0, 0 << 24 | 1, 0) gives the kind (integer below 3), the edge's free or
+ * the face's fixed coordinate e (integer below d) and the position t
+ * (uniform); counter (i, 0, 0 << 24 | 1, 1) gives one bit per coordinate
+ * choosing its bound (hi for 1), from the first word for coordinates 0..31
+ * and the second for 32..63. */
+static void ray_seed_point(const orc_problem *P, const orc_config *C, int i, double *x)
+{
+    int d = P->d;
+    uint32_t a[4], b[4];
+    draw4(C, (uint32_t)i, 0, ((uint32_t)PH_INIT << 24) | 1u, 0, a);
+    draw4(C, (uint32_t)i, 0, ((uint32_t)PH_INIT << 24) | 1u, 1, b);
+    uint32_t kind = uint_below(a[0], 3);
+    int e = (int)uint_below(a[1], (uint32_t)d);
+    double t = orc_u01(a[2]);
+    for (int c = 0; c < d; ++c) {
+        double lo = P->lo[c], hi = P->hi[c];
+        /* the anchor's coordinate: at the middle or at a bound */
+        int middle = (kind == 1 && c == e) || (kind == 2 && c != e);
+        int up = (int)(((c < 32 ? b[0] : b[1]) >> (c & 31)) & 1u);
+        double anchor = middle ? 0.5 * (lo + hi) : (up ? hi : lo);
+        double centre = 0.5 * (lo + hi);
+        /* t along anchor -> opposite anchor (2 centre - anchor) */
+        x[c] = anchor + t * (2.0 * centre - 2.0 * anchor);
+    }
+}
+
 void orc_init_population(const orc_problem *P, const orc_config *C, double *X)
 {
     int d = P->d;
+    if (C->flags & 4u) {
+        for (int i = 0; i < C->N; ++i) ray_seed_point(P, C, i, X + (size_t)i * d);
+        return;
+    }
     for (int i = 0; i < C->N; ++i) {
         for (int blk = 0; 4 * blk < d; ++blk) {
             uint32_t o[4];

@@ -52,7 +52,7 @@ class _Config(C.Structure):
                 ("sigma_c", C.c_double), ("grad_mode", C.c_int32), ("fd_h", C.c_double),
                 ("ls_c1", C.c_double), ("ls_max", C.c_int32), ("curv_eps", C.c_double),
                 ("gate_reps", C.c_int32), ("phase_mask", C.c_uint32), ("seed", C.c_uint64),
-                ("problem_id", C.c_uint32)]
+                ("problem_id", C.c_uint32), ("flags", C.c_uint32)]
 
 
 class _State(C.Structure):
@@ -178,7 +178,7 @@ def make_config(cfg, d: int) -> _Config:
     return _Config(cfg.N, cfg.m, cfg.n_osc, conv_steps(cfg, d), cfg.n_anti, cfg.n_cloud, cfg.M, cfg.eps_grad,
                    cfg.eps_dup, cfg.log_delta, cfg.momentum, cfg.alpha, cfg.sigma, cfg.sigma_c, cfg.grad_mode,
                    cfg.fd_h, cfg.ls_c1, cfg.ls_max, cfg.curv_eps, cfg.gate_reps, cfg.phase_mask, cfg.seed,
-                   cfg.problem_id)
+                   cfg.problem_id, int(getattr(cfg, "flags", 0)))
 
 
 @dataclass

@@ -9,9 +9,11 @@ LIB_PATH = os.path.join(HERE, "libchisao.so")
 
 OK, E_INVAL, E_NOMEM, E_DEVICE, E_STATE, E_RANGE = 0, -1, -2, -3, -4, -5
 GAUSS, STUDENT_T = 0, 1
+RASTRIGIN, ACKLEY, SCHWEFEL, STYBLINSKI_TANG, MICHALEWICZ, TRID, BUKIN6 = 2, 3, 4, 5, 6, 7, 8
 GRAD_FD, GRAD_ADJOINT = 0, 1
 FLAG_NO_GRAPH = 1
 FLAG_NO_AUTOTUNE = 2
+FLAG_RAY_SEEDING = 4
 TUNE_VARIANTS = 4
 
 

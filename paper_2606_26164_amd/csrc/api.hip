@@ -344,6 +344,7 @@ extern "C" int chisao_init_batched(chisao_handle *out, int n_problems, const chi
             q.key0 = (uint32_t)(c.seed & 0xFFFFFFFFu);
             q.key1 = (uint32_t)(c.seed >> 32) ^ c.problem_id;
             q.phase_mask = c.phase_mask;
+            q.ray_seed = (c.flags & CHISAO_FLAG_RAY_SEEDING) != 0;
             q.noise_sigma = pr.noise_sigma;
             q.gate_reps = c.gate_reps > 0 ? c.gate_reps : c.M;
             {

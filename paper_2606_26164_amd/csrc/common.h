@@ -141,6 +141,7 @@ struct ProblemDesc {
     int m, n_conv, n_anti, n_cloud, M, ls_max, grad_mode;
     float eps_grad, eps_dup, log_delta, momentum, alpha, sigma_cfg, sigma_c, fd_h, ls_c1, curv_eps;
     uint32_t key0, key1, phase_mask;
+    int ray_seed;       // starting population on rays through the box centre (when none is given)
     float noise_sigma;  // additive evaluation noise (0: none)
     int gate_reps;      // noisy evaluations averaged by the quality gate
     int hk0;            // offset of the problem's 2^hash_lb + 1 deduplication bucket offsets in Dev::hoff

@@ -37,19 +37,38 @@ hipError_t launch_fill_u8(uint8_t *p, uint8_t v, size_t n, hipStream_t st) {
     return hipGetLastError();
 }
 
-// Uniform starting population in the box from the INIT stream (counter =
-// sample index within its problem).
+// Starting population from the INIT stream (counter = sample index within its
+// problem): uniform in the box, or on rays through the box centre from its
+// vertices, edge midpoints and face centres (structured ray seeding, Sec.
+// 5.3; the layout of the draws is stated with CHISAO_FLAG_RAY_SEEDING).
 __global__ void uniform_init_kernel(Dev D) {
     const int nb = (D.DS + 3) / 4;
     for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < (long)D.NT * nb; e += (long)gridDim.x * blockDim.x) {
         const int s = (int)(e / nb), blk = (int)(e % nb);
         const ProblemDesc &pd = D.pd[D.pid[s]];
         if (4 * blk >= pd.d) continue;
-        uint4 o = philox((uint32_t)(s - pd.s0), 0u, kInit << 24, (uint32_t)blk, pd.key0, pd.key1);
-        const uint32_t w[4] = {o.x, o.y, o.z, o.w};
+        const uint32_t i = (uint32_t)(s - pd.s0);
+        if (!pd.ray_seed) {
+            uint4 o = philox(i, 0u, kInit << 24, (uint32_t)blk, pd.key0, pd.key1);
+            const uint32_t w[4] = {o.x, o.y, o.z, o.w};
+            for (int q = 0; q < 4; ++q) {
+                const int c = 4 * blk + q;
+                if (c < pd.d) D.X[(size_t)s * D.DS + c] = pd.lo[c] + u01(w[q]) * (pd.hi[c] - pd.lo[c]);
+            }
+            continue;
+        }
+        const uint4 a = philox(i, 0u, (kInit << 24) | 1u, 0u, pd.key0, pd.key1);
+        const uint4 b = philox(i, 0u, (kInit << 24) | 1u, 1u, pd.key0, pd.key1);
+        const uint32_t kind = uint_below(a.x, 3u);  // 0 vertex, 1 edge midpoint, 2 face centre
+        const int ec = (int)uint_below(a.y, (uint32_t)pd.d);
+        const float t = u01(a.z);
         for (int q = 0; q < 4; ++q) {
             const int c = 4 * blk + q;
-            if (c < pd.d) D.X[(size_t)s * D.DS + c] = pd.lo[c] + u01(w[q]) * (pd.hi[c] - pd.lo[c]);
+            if (c >= pd.d) break;
+            const float lo = pd.lo[c], w = pd.hi[c] - lo;
+            const bool middle = (kind == 1u && c == ec) || (kind == 2u && c != ec);
+            const bool up = (((c < 32 ? b.x : b.y) >> (c & 31)) & 1u) != 0u;
+            D.X[(size_t)s * D.DS + c] = middle ? lo + 0.5f * w : (up ? pd.hi[c] - t * w : lo + t * w);
         }
     }
 }

@@ -32,6 +32,27 @@ def test_library_exports_every_declared_symbol():
     assert set(_declared_functions()) == set(_lib.EXPORTS)
 
 
+def test_header_constants_match_the_binding():
+    """Every integer #define of the header has the same value in _lib."""
+    from paper_2606_26164_amd import _lib
+
+    text = open(HEADER).read()
+    defs = dict(re.findall(r"#define CHISAO_([A-Z0-9_]+)\s+\(?(-?\d+)u?\)?", text))
+    assert len(defs) >= 20
+    for name, val in defs.items():
+        if name in ("PROF_CLASSES",):
+            assert _lib.PROF_CLASSES == int(val)
+            continue
+        if name.startswith("PROF_"):
+            assert _lib.PROF_NAMES[int(val)] == name[5:].lower(), name
+            continue
+        if name == "TUNE_VARIANTS":
+            assert _lib.TUNE_VARIANTS == int(val)
+            continue
+        assert hasattr(_lib, name), name
+        assert getattr(_lib, name) == int(val), name
+
+
 def test_ctypes_struct_layouts_match_header():
     """Compile a tiny C program that prints sizeof/offsetof of the header's
     structs and compare with the ctypes declarations."""
