@@ -220,6 +220,18 @@ int chisao_cycle(chisao_handle h, int n_cycles, chisao_cycle_stats *stats_host);
  * returned.  problem: index within the handle. */
 int chisao_modes(chisao_handle h, int problem, float *x_out, float *f_out, int cap, int *n_out);
 
+/* Widths of the modes (Sec. 3.2 Phase 3: the surviving sample's inverse
+ * Hessian estimate is preserved for width estimation).  For each mode, in
+ * the order of chisao_modes, the diagonal of the L-BFGS inverse-Hessian
+ * approximation H of -f built from the pairs of the Phase 1 in which the
+ * sample converged: H = gamma I updated by every stored pair from oldest to
+ * newest, gamma = s'y / y'y of the newest pair (1 / max(|grad f|_2, 1) for a
+ * sample that stuck without any pair).  For a peak of a Gaussian mixture
+ * these approximate the component variances along the coordinates.
+ * Synchronizes; writes w_out (host [cap*d]); *n_out receives the mode count;
+ * if cap is smaller, nothing is written and CHISAO_E_RANGE is returned. */
+int chisao_mode_widths(chisao_handle h, int problem, float *w_out, int cap, int *n_out);
+
 /* Copy the state to / from host memory (synchronizes).  set_state writes X,
  * stuck, active, k and the Golden Rooster state; F, G and the decision arrays
  * are recomputed by the next cycle. */

@@ -84,6 +84,8 @@ typedef struct {
     double f_max, sigma, alpha_c, alpha_a;
     int32_t K_lost, n_stuck, n_modes, reseed_kind, n_free, n_unfrozen;
     double *Fg; /* quality-gate values (noisy objectives only) */
+    double *W;       /* N*d preserved inverse-Hessian diagonals (width export), or NULL */
+    uint8_t *wvalid; /* N: W holds a value */
 } orc_state;
 
 typedef struct {
@@ -909,6 +911,48 @@ int orc_phase_stick(const orc_problem *P, const double *logc, const orc_config *
 /* strict order (higher f first, then lower index).  Every stuck sample,     */
 /* removed or not, takes part in the comparison.                             */
 /* ------------------------------------------------------------------------ */
+/* Width export (Phase 3: the surviving sample's inverse Hessian estimate is
+ * preserved for width estimation).  The estimate is the L-BFGS inverse
+ * Hessian of F = -f that the sample's pairs define, i.e. the matrix the
+ * two-loop recursion applies; its diagonal is read off by applying the
+ * two-loop to each unit vector.  Survivors with pairs (from this cycle's
+ * Phase 1) are refreshed; a survivor without pairs keeps the diagonal it
+ * had, or, if it never had one, takes the two-loop's initial matrix for an
+ * empty history, 1 / max(|grad f|_2, 1) times I. */
+static void preserve_widths(const orc_problem *P, const orc_config *C, orc_state *S)
+{
+    int d = P->d, m = C->m;
+    if (!S->W || !S->wvalid) return;
+#pragma omp parallel
+    {
+        double *e = (double *)malloc(sizeof(double) * d);
+        double *p = (double *)malloc(sizeof(double) * d);
+        double *al = (double *)malloc(sizeof(double) * m);
+#pragma omp for schedule(dynamic, 16)
+        for (int i = 0; i < C->N; ++i) {
+            if (!(S->stuck[i] && S->active[i])) continue;
+            double *w = S->W + (size_t)i * d;
+            if (S->cnt[i] > 0) {
+                for (int j = 0; j < d; ++j) {
+                    /* the two-loop returns -H(-g); with g = -e_j it returns -H e_j */
+                    for (int k = 0; k < d; ++k) e[k] = (k == j) ? -1.0 : 0.0;
+                    orc_two_loop(d, m, S->cnt[i], S->head[i], S->S + (size_t)i * m * d, S->Y + (size_t)i * m * d,
+                                 S->rho + (size_t)i * m, e, p, al);
+                    w[j] = -p[j];
+                }
+                S->wvalid[i] = 1;
+            } else if (!S->wvalid[i]) {
+                double g0 = 1.0 / fmax(nrm2(d, S->G + (size_t)i * d), 1.0);
+                for (int j = 0; j < d; ++j) w[j] = g0;
+                S->wvalid[i] = 1;
+            }
+        }
+        free(e);
+        free(p);
+        free(al);
+    }
+}
+
 int orc_phase_dedup(const orc_problem *P, const orc_config *C, orc_state *S, orc_replay *R)
 {
     int N = C->N, d = P->d;
@@ -958,6 +1002,7 @@ int orc_phase_dedup(const orc_problem *P, const orc_config *C, orc_state *S, orc
     fold_replay(R, sr, N);
     free(sr);
     free(rem);
+    preserve_widths(P, C, S);
     /* Golden Rooster bookkeeping: a generation that found no new peak counts
      * as a failure; two in a row disable it for good. */
     if (S->gr_used_last) {
@@ -1122,6 +1167,7 @@ int orc_phase_reseed(const orc_problem *P, const orc_config *C, orc_state *S)
         S->stuck[s] = 0;
         S->cnt[s] = 0;
         S->head[s] = m - 1;
+        if (S->wvalid) S->wvalid[s] = 0;
         for (int l = 0; l < d; ++l) S->V[(size_t)s * d + l] = 0.0;
     }
     free(freel);

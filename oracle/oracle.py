@@ -64,7 +64,7 @@ class _State(C.Structure):
                 ("sigma", C.c_double), ("alpha_c", C.c_double), ("alpha_a", C.c_double),
                 ("K_lost", C.c_int32), ("n_stuck", C.c_int32), ("n_modes", C.c_int32),
                 ("reseed_kind", C.c_int32), ("n_free", C.c_int32), ("n_unfrozen", C.c_int32),
-                ("Fg", C.c_void_p)]
+                ("Fg", C.c_void_p), ("W", C.c_void_p), ("wvalid", C.c_void_p)]
 
 
 class _Replay(C.Structure):
@@ -222,10 +222,14 @@ class OracleRun:
         self.cnt = np.zeros(N, np.int32)
         self.trace = np.full((self.cc.n_conv + 1, N), TR_NONE, np.uint8)
         self.Fg = np.zeros(N)
+        self.W = np.zeros((N, d))
+        self.wvalid = np.zeros(N, np.uint8)
         self.st = _State(_ptr(self.X), _ptr(self.F), _ptr(self.G), _ptr(self.V), _ptr(self.stuck),
                          _ptr(self.active), _ptr(self.conv), _ptr(self.removed), _ptr(self.S), _ptr(self.Y),
                          _ptr(self.rho), _ptr(self.head), _ptr(self.cnt), 0, 0, 0, 0, 0)
         self.st.Fg = _ptr(self.Fg)
+        self.st.W = _ptr(self.W)
+        self.st.wvalid = _ptr(self.wvalid)
 
     @property
     def k(self) -> int:
@@ -311,6 +315,11 @@ class OracleRun:
         idx = np.nonzero(self.stuck & self.active)[0]
         fv = self.Fg if self.P.noise_sigma > 0 else self.F
         return self.X[idx].copy(), fv[idx].copy(), idx
+
+    def mode_widths(self):
+        """Preserved inverse-Hessian diagonals of the modes, in the order of modes()."""
+        idx = np.nonzero(self.stuck & self.active)[0]
+        return self.W[idx].copy()
 
     def stats(self) -> dict:
         s = self.st

@@ -61,8 +61,9 @@ class KernelProfile(C.Structure):
 PROF_CLASSES = 8
 PROF_NAMES = ("eval_direct", "eval_trial", "eval_probe", "eval_fd", "lbfgs", "lbfgs_pairs", "unused6", "unused7")
 
-EXPORTS = ("chisao_init", "chisao_init_batched", "chisao_profile", "chisao_cycle", "chisao_modes", "chisao_get_state", "chisao_set_state",
-           "chisao_run_phases", "chisao_eval", "chisao_destroy", "chisao_last_error", "chisao_tuning")
+EXPORTS = ("chisao_init", "chisao_init_batched", "chisao_profile", "chisao_cycle", "chisao_modes",
+           "chisao_mode_widths", "chisao_get_state", "chisao_set_state", "chisao_run_phases", "chisao_eval",
+           "chisao_destroy", "chisao_last_error", "chisao_tuning")
 
 _lib = None
 
@@ -84,6 +85,8 @@ def load(path: str = LIB_PATH):
     L.chisao_cycle.restype = C.c_int
     L.chisao_modes.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int, P(C.c_int)]
     L.chisao_modes.restype = C.c_int
+    L.chisao_mode_widths.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_int, P(C.c_int)]
+    L.chisao_mode_widths.restype = C.c_int
     L.chisao_get_state.argtypes = [C.c_void_p, C.c_int, P(State)]
     L.chisao_get_state.restype = C.c_int
     L.chisao_set_state.argtypes = [C.c_void_p, C.c_int, P(State)]

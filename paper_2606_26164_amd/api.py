@@ -154,6 +154,18 @@ class Optimizer:
                 "chisao_modes")
         return ModeSet(X, F)
 
+    def mode_widths(self, problem: int = 0) -> np.ndarray:
+        """Per mode (in the order of ``modes``) the preserved inverse-Hessian
+        diagonal of -f: squared widths along the coordinates."""
+        n = C.c_int(0)
+        rc = self.lib.chisao_mode_widths(self.h, problem, None, 0, C.byref(n))
+        if rc not in (L.OK, L.E_RANGE):
+            L.check(rc, "chisao_mode_widths")
+        Wd = np.zeros((n.value, self.specs[problem].d), np.float32)
+        L.check(self.lib.chisao_mode_widths(self.h, problem, Wd.ctypes.data, n.value, C.byref(n)),
+                "chisao_mode_widths")
+        return Wd
+
     def get_state(self, history: bool = False, problem: int = 0) -> dict:
         sp = self.specs[problem]
         N, d, m = sp.N, sp.d, sp.m

@@ -415,6 +415,8 @@ extern "C" int chisao_init_batched(chisao_handle *out, int n_problems, const chi
         ALLOC(D.Gh, float, N * DSz);
         ALLOC(D.ginf, float, N);
         ALLOC(D.Fg, float, N);
+        ALLOC(D.Wd, float, N * DSz);
+        ALLOC(D.wvalid, uint8_t, N);
         if (any_fd) ALLOC(D.Gp, float, N * (size_t)Mmax * DSz);
         ALLOC(D.stuck, uint8_t, N);
         ALLOC(D.active, uint8_t, N);
@@ -440,6 +442,8 @@ extern "C" int chisao_init_batched(chisao_handle *out, int n_problems, const chi
         ALLOC(D.part, double, P * (size_t)D.n_part_blocks * 129);
         ALLOC(D.prof, unsigned long long, kProfClasses);
         HIP_GO(hipMemsetAsync(D.X, 0, sizeof(float) * N * DSz, st));
+        HIP_GO(hipMemsetAsync(D.Wd, 0, sizeof(float) * N * DSz, st));
+        HIP_GO(hipMemsetAsync(D.wvalid, 0, N, st));
         HIP_GO(launch_uniform_init(D, st));
         if (x0_dev) {
             for (int p = 0; p < n_problems; ++p)
@@ -966,6 +970,28 @@ extern "C" int chisao_modes(chisao_handle h, int problem, float *x_out, float *f
     HIP_TRY(hipMemcpyAsync(x_out, D.Gh + (size_t)q.s0 * D.DS, sizeof(float) * (size_t)n * q.d, hipMemcpyDeviceToHost,
                            h->stream));
     if (f_out) HIP_TRY(hipMemcpyAsync(f_out, D.Pd + q.s0, sizeof(float) * (size_t)n, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return CHISAO_OK;
+}
+
+extern "C" int chisao_mode_widths(chisao_handle h, int problem, float *w_out, int cap, int *n_out) {
+    if (!h || !n_out) return fail(CHISAO_E_INVAL, "null argument");
+    int rc = check_problem(h, problem);
+    if (rc) return rc;
+    const Dev &D = h->D;
+    const ProblemDesc &q = h->pdh[problem];
+    HIP_TRY(hipSetDevice(h->device));
+    HIP_TRY(launch_width_list(D, problem, q.N, h->stream));
+    Ctl c;
+    HIP_TRY(hipMemcpyAsync(&c, D.ctl + problem, sizeof c, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    const int n = c.count[O_PEAKS];
+    *n_out = n;
+    if (cap < n) return fail(CHISAO_E_RANGE, "capacity %d < %d modes", cap, n);
+    if (n == 0) return CHISAO_OK;
+    if (!w_out) return fail(CHISAO_E_INVAL, "null w_out");
+    HIP_TRY(hipMemcpyAsync(w_out, D.Gh + (size_t)q.s0 * D.DS, sizeof(float) * (size_t)n * q.d, hipMemcpyDeviceToHost,
+                           h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
     return CHISAO_OK;
 }

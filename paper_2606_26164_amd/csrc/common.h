@@ -200,6 +200,8 @@ struct Dev {
     // population state (rows of stride DS)
     float *X, *F, *G, *V, *Xprev, *Gprev, *Pd, *Gh, *Gp, *ginf;
     float *Fg;  // quality-gate values of noisy problems
+    float *Wd;         // [NT][DS] preserved inverse-Hessian diagonal of each surviving mode (width export)
+    uint8_t *wvalid;   // [NT] Wd holds a value
     uint8_t *stuck, *active, *conv, *removed, *stuck_pre, *status, *reset, *steep, *trace;
     float *S, *Y, *rho;      // [NT][mmax][DS], [NT][mmax]
     int *head, *cnt;

@@ -689,6 +689,104 @@ __global__ void dedup_finalize_kernel(Dev D) {
     }
 }
 
+// Width export.  The survivor of deduplication keeps its inverse-Hessian
+// estimate for width estimation (Phase 3): H approximates the inverse
+// Hessian of F = -f from the sample's L-BFGS pairs, and diag(H) is kept.  H
+// is formed by the BFGS recursion
+//   H <- H - rho (H y s^T + s y^T H) + (rho^2 y^T H y + rho) s s^T
+// over the pairs from oldest to newest, from gamma I with gamma = s'y / y'y
+// of the newest pair (the two-loop's initial matrix), held in LDS by one
+// workgroup per survivor.  Only survivors whose pairs come from this cycle's
+// Phase 1 are recomputed: a sample that was stuck before is released with an
+// empty history and sticks again without a step, so it keeps the diagonal it
+// had; a survivor that never had a pair gets gamma0 = 1 / max(|g|_2, 1).
+constexpr int kWidthBlock = 256;
+__global__ __launch_bounds__(kWidthBlock) void width_kernel(Dev D) {
+    __shared__ float H[64 * 64];
+    __shared__ float sv[64], yv[64], wv[64];
+    __shared__ float red[kWidthBlock];
+    const int tid = threadIdx.x;
+    for (int s = blockIdx.x; s < D.NT; s += gridDim.x) {
+        if (!(D.stuck[s] && D.active[s])) continue;
+        const ProblemDesc &pd = D.pd[D.pid[s]];
+        if (!((pd.phase_mask >> 3) & 1)) continue;
+        const int d = pd.d, m = pd.m, cnt = D.cnt[s], head = D.head[s];
+        const size_t mx = (size_t)D.mmax;
+        float *wrow = D.Wd + (size_t)s * D.DS;
+        if (cnt == 0) {
+            if (D.wvalid[s]) continue;
+            float g2 = 0.0f;
+            for (int c = tid; c < d; c += kWidthBlock) g2 += D.G[(size_t)s * D.DS + c] * D.G[(size_t)s * D.DS + c];
+            red[tid] = g2;
+            __syncthreads();
+            for (int o = kWidthBlock / 2; o > 0; o >>= 1) {
+                if (tid < o) red[tid] += red[tid + o];
+                __syncthreads();
+            }
+            const float gamma0 = 1.0f / fmaxf(sqrtf(red[0]), 1.0f);
+            for (int c = tid; c < d; c += kWidthBlock) wrow[c] = gamma0;
+            if (tid == 0) D.wvalid[s] = 1;
+            __syncthreads();
+            continue;
+        }
+        // gamma from the newest pair
+        {
+            const size_t off = ((size_t)s * mx + head) * D.DS;
+            float a = 0.0f, b = 0.0f;
+            for (int c = tid; c < d; c += kWidthBlock) {
+                const float y = D.Y[off + c];
+                a += D.S[off + c] * y;
+                b += y * y;
+            }
+            red[tid] = a;
+            __syncthreads();
+            for (int o = kWidthBlock / 2; o > 0; o >>= 1) {
+                if (tid < o) red[tid] += red[tid + o];
+                __syncthreads();
+            }
+            const float sy = red[0];
+            __syncthreads();
+            red[tid] = b;
+            __syncthreads();
+            for (int o = kWidthBlock / 2; o > 0; o >>= 1) {
+                if (tid < o) red[tid] += red[tid + o];
+                __syncthreads();
+            }
+            const float gamma = sy / red[0];
+            for (int e = tid; e < d * d; e += kWidthBlock) H[e] = (e / d == e % d) ? gamma : 0.0f;
+            __syncthreads();
+        }
+        for (int k = cnt - 1; k >= 0; --k) {
+            const int slot = (head - k + m) % m;
+            const size_t off = ((size_t)s * mx + slot) * D.DS;
+            const float rho = D.rho[(size_t)s * mx + slot];
+            for (int c = tid; c < d; c += kWidthBlock) {
+                sv[c] = D.S[off + c];
+                yv[c] = D.Y[off + c];
+            }
+            __syncthreads();
+            // w = H y
+            for (int r = tid; r < d; r += kWidthBlock) {
+                float acc = 0.0f;
+                for (int c = 0; c < d; ++c) acc += H[r * d + c] * yv[c];
+                wv[r] = acc;
+            }
+            __syncthreads();
+            float yw = 0.0f;
+            for (int c = 0; c < d; ++c) yw += yv[c] * wv[c];
+            const float coef = rho * rho * yw + rho;
+            for (int e = tid; e < d * d; e += kWidthBlock) {
+                const int r = e / d, c = e % d;
+                H[e] += -rho * (wv[r] * sv[c] + sv[r] * wv[c]) + coef * sv[r] * sv[c];
+            }
+            __syncthreads();
+        }
+        for (int c = tid; c < d; c += kWidthBlock) wrow[c] = H[c * d + c];
+        if (tid == 0) D.wvalid[s] = 1;
+        __syncthreads();
+    }
+}
+
 // Golden Rooster generations: a generation that found no new peak counts
 // as a failure; two in a row disable it for the rest of the run.
 __global__ void gr_book_kernel(Dev D) {
@@ -714,6 +812,7 @@ hipError_t launch_dedup(const Dev &D, hipStream_t st) {
     hipLaunchKernelGGL(dedup_scatter_kernel, per_sample, dim3(kBlock), 0, st, D);
     hipLaunchKernelGGL(dedup_scan_kernel, per_wave, dim3(kBlock), 0, st, D);
     hipLaunchKernelGGL(dedup_finalize_kernel, dim3(grid_for(D.NT, kBlock, 1024)), dim3(kBlock), 0, st, D);
+    hipLaunchKernelGGL(width_kernel, dim3(grid_for(D.NT, 1, 2048)), dim3(kWidthBlock), 0, st, D);
     hipLaunchKernelGGL(gr_book_kernel, dim3(grid_for(D.P, 64)), dim3(64), 0, st, D);
     return hipGetLastError();
 }
@@ -918,6 +1017,7 @@ __global__ void reseed_finalize_kernel(Dev D) {
         D.stuck[s] = 0;  // removed[] keeps the deduplication decisions until the next cycle
         D.cnt[s] = 0;
         D.head[s] = pd.m - 1;
+        D.wvalid[s] = 0;
         for (int c = 0; c < pd.d; ++c) D.V[(size_t)s * D.DS + c] = 0.0f;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0 && kind == 2) {
@@ -1207,6 +1307,24 @@ __global__ void gather_modes_kernel(Dev D, int p) {
         xo[(size_t)j * pd.d + c] = D.X[(size_t)s * D.DS + c];
         if (c == 0) D.Pd[pd.s0 + j] = gate_values(D, pd)[s];
     }
+}
+
+// the preserved inverse-Hessian diagonals of problem p's modes, in the mode order
+__global__ void gather_widths_kernel(Dev D, int p) {
+    const ProblemDesc &pd = D.pd[p];
+    const int n = D.ctl[p].count[O_PEAKS];
+    const int *lst = list_ptr(D, O_PEAKS, pd.s0);
+    float *wo = D.Gh + (size_t)pd.s0 * D.DS;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < (long)n * pd.d; e += (long)gridDim.x * blockDim.x) {
+        const int j = (int)(e / pd.d), c = (int)(e % pd.d);
+        wo[(size_t)j * pd.d + c] = D.Wd[(size_t)lst[j] * D.DS + c];
+    }
+}
+
+hipError_t launch_width_list(const Dev &D, int p, int N, hipStream_t st) {
+    hipLaunchKernelGGL(ordered_lists_kernel, dim3(1), dim3(kScanThreads), 0, st, D, p);
+    hipLaunchKernelGGL(gather_widths_kernel, dim3(grid_for((long)N * D.DS, kBlock, 4096)), dim3(kBlock), 0, st, D, p);
+    return hipGetLastError();
 }
 
 hipError_t launch_mode_list(const Dev &D, int p, int s0, int N, hipStream_t st) {

@@ -82,6 +82,7 @@ hipError_t launch_hlc_update(const Dev &D, int step, hipStream_t st);
 hipError_t launch_anti_update(const Dev &D, int step, hipStream_t st);
 hipError_t launch_end_cycle(const Dev &D, int advance, hipStream_t st);
 hipError_t launch_mode_list(const Dev &D, int p, int s0, int N, hipStream_t st);
+hipError_t launch_width_list(const Dev &D, int p, int N, hipStream_t st);
 // Mode export of problem p: its stuck active samples in ascending index, rows
 // to D.Gh and values to D.Pd from row/element s0, count in ctl[p].count[O_PEAKS].
 

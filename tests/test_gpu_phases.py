@@ -358,3 +358,48 @@ def test_dedup_pairs_across_hash_cells_match_oracle():
     run.phase_stick()
     run.phase_dedup()
     np.testing.assert_array_equal(run.removed.astype(bool), removed)
+
+
+def test_mode_widths_match_oracle_from_the_same_history():
+    """Width export: after Phases 1-3 the GPU's preserved inverse-Hessian
+    diagonals of the modes (BFGS recursion in LDS, FP32) against the oracle's
+    (two-loop on unit vectors, FP64) from the GPU's own pairs."""
+    prob, cfg, x0 = _many_stuck_case()
+    with _gpu(prob, cfg, x0) as opt:
+        opt.run_phases(1 << 1)
+        g1 = opt.get_state(history=True)
+        opt.run_phases((1 << 2) | (1 << 3))
+        g3 = opt.get_state()
+        ms = opt.modes()
+        wg = opt.mode_widths().astype(np.float64)
+    run = _oracle_from(prob, cfg, g1)
+    for f in ("S", "Y", "rho", "head", "cnt"):
+        getattr(run, f)[:] = g1[f]
+    r2 = run.phase_stick(stuck_in=g3["stuck_pre"], **REPLAY)
+    r3 = run.phase_dedup(removed_in=g3["removed"], **REPLAY)
+    assert r2.n_hard == 0 and r3.n_hard == 0
+    wo = run.mode_widths()
+    assert wg.shape == wo.shape and len(wo) == len(ms.F) and len(wo) > 0
+    assert np.all(wg > 0) and np.all(np.isfinite(wg))
+    rel = np.abs(wg - wo).max(1) / np.abs(wo).max(1)
+    print(f"\n{len(wo)} modes: width relative error max {rel.max():.2e}")
+    assert rel.max() < 1e-3
+
+
+def test_mode_widths_of_isotropic_peaks_are_the_variance():
+    """Well separated isotropic Gaussian peaks (variance 0.5): near a peak the
+    curvature pairs satisfy y = s / 0.5, so every preserved diagonal is the
+    variance.  A whole run (3 cycles): modes found in earlier cycles keep the
+    diagonal from the cycle they converged in."""
+    from paper_2606_26164_amd.api import Optimizer
+
+    prob = W.mixture_problem(12, 6, 4, 8.0, isotropic_var=0.5, dirichlet=None)
+    cfg = W.RunConfig(N=400, m=8, n_osc=3, n_conv=20, eps_grad=1e-3, grad_mode=1, seed=12)
+    x0 = W.uniform_population(12, 400, prob.lo, prob.hi)
+    with Optimizer(prob, cfg, x0) as opt:
+        opt.cycle(cfg.n_osc)
+        ms = opt.modes()
+        wg = opt.mode_widths().astype(np.float64)
+    print(f"\n{len(ms.F)} modes, widths in [{wg.min():.4f}, {wg.max():.4f}]")
+    assert len(ms.F) >= 2
+    assert np.all(np.abs(wg - 0.5) < 0.05 * 0.5)
