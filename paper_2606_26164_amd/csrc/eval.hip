@@ -234,6 +234,13 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
     __shared__ int s_pass[PPW];
     __shared__ int s_acc[PPW];
     __shared__ int s_pref[kMaxClass + 1];
+    // line search: each point's sample row and gradient before the step, and
+    // the partial sums of g . (x_trial - x) over blocks of four coordinates,
+    // all gathered while the points are generated
+    constexpr bool TRIAL = CENTER == kTrial;
+    __shared__ float s_x0[TRIAL ? PPW * LD : 1];
+    __shared__ float s_g0[TRIAL ? PPW * LD : 1];
+    __shared__ float s_dp[TRIAL ? PPW * KS : 1];
 
     const Dev &D = a.D;
     const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
@@ -323,11 +330,13 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
             s_den[pt] = 1.0f;
         }
         __syncthreads();
-        // ---- generate the points (zero padded to DP) -----------------------
-        for (int e = lead ? lane : PPW * KS; e < PPW * KS; e += kWave) {
+        // ---- generate the points (zero padded to DP), all waves -------------
+        for (int e = threadIdx.x; e < PPW * KS; e += blockDim.x) {
             const int pt = e / KS, blk = e % KS, c0 = 4 * blk;
             const int s = s_s[pt];
             float x[4] = {0.f, 0.f, 0.f, 0.f};
+            float x0[4] = {0.f, 0.f, 0.f, 0.f}, g0[4] = {0.f, 0.f, 0.f, 0.f};
+            float dp = 0.0f;
             if (s >= 0) {
                 const int ci = s_c[pt];
                 float z[4] = {0.f, 0.f, 0.f, 0.f};
@@ -344,7 +353,10 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
                         float xv = a.X[(size_t)s * xs + c];
                         if constexpr (CENTER == kTrial) {
                             const float t = ldexpf(1.0f, -(r0 + ci));
+                            x0[q] = xv;
+                            g0[q] = D.G[(size_t)s * D.DS + c];
                             xv = fminf(fmaxf(xv + t * D.Pd[(size_t)s * D.DS + c], pd.lo[c]), pd.hi[c]);
+                            dp += g0[q] * (xv - x0[q]);
                         } else if constexpr (CENTER == kProbe) {
                             const float sgn = (ci & 1) ? -1.0f : 1.0f;
                             xv = xv + sigma * sgn * z[q];
@@ -366,6 +378,14 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
             }
 #pragma unroll
             for (int q = 0; q < 4; ++q) s_pts[pt * LD + c0 + q] = x[q];
+            if constexpr (TRIAL) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    s_x0[pt * LD + c0 + q] = x0[q];
+                    s_g0[pt * LD + c0 + q] = g0[q];
+                }
+                s_dp[pt * KS + blk] = dp;
+            }
         }
         __syncthreads();
         // Noisy problems: every value the method sees carries sigma_n z, z the
@@ -634,8 +654,7 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
                 const int pt = lane >> 1, h = lane & 1, s = s_s[pt];
                 float dot = 0.0f;
                 if (s >= 0)
-                    for (int c = h; c < d; c += 2)
-                        dot += D.G[(size_t)s * DS + c] * (s_pts[pt * LD + c] - D.X[(size_t)s * DS + c]);
+                    for (int b = h; b < KS; b += 2) dot += s_dp[pt * KS + b];
                 dot += __shfl_xor(dot, 1, kWave);
                 // (relaxed by twice the noise level for noisy objectives: the
                 // noise-aware Armijo test of Berahas, Byrd and Nocedal 2019)
@@ -652,14 +671,14 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
                 s_acc[lane] = r;
             }
             __syncthreads();
-            for (int e = lead ? lane : jpw * d; e < jpw * d; e += kWave) {
+            for (int e = threadIdx.x; e < jpw * d; e += blockDim.x) {
                 const int j = e / d, c = e % d, p0 = j * Vc, s = s_s[p0];
                 if (s >= 0 && s_acc[j] >= 0) {
                     const int pa = p0 + s_acc[j];
                     const size_t o = (size_t)s * DS + c;
-                    D.Xprev[o] = D.X[o];
+                    D.Xprev[o] = s_x0[p0 * LD + c];
                     D.X[o] = s_pts[pa * LD + c];
-                    D.Gprev[o] = D.G[o];
+                    D.Gprev[o] = s_g0[p0 * LD + c];
                     if constexpr (GRAD) D.G[o] = s_g[pa * LD + c];
                 }
             }
