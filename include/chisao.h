@@ -168,6 +168,8 @@ typedef struct {
     uint8_t *conv;      /* [N] last Phase 1: 1 converged, 2 stalled (a search from an empty history failed,
                            so every later iteration would repeat it; never with noise), 0 otherwise */
     float *Fg;          /* [N] quality-gate values of a noisy problem after Phase 1 (get only) */
+    float *Wd;          /* [N*d] preserved inverse-Hessian diagonals (width export; see chisao_mode_widths) */
+    uint8_t *wvalid;    /* [N] 1 where Wd holds a value */
 } chisao_state;
 
 /* Kernel timing of the work enqueued by chisao_cycle / chisao_run_phases
@@ -233,8 +235,10 @@ int chisao_modes(chisao_handle h, int problem, float *x_out, float *f_out, int c
 int chisao_mode_widths(chisao_handle h, int problem, float *w_out, int cap, int *n_out);
 
 /* Copy the state to / from host memory (synchronizes).  set_state writes X,
- * stuck, active, k and the Golden Rooster state; F, G and the decision arrays
- * are recomputed by the next cycle. */
+ * stuck, active, k, the Golden Rooster state and the preserved widths; F, G,
+ * the histories and the decision arrays are recomputed by the next cycle.
+ * Between cycles this is the whole state a run carries forward: a handle
+ * given it continues exactly as the handle it was read from. */
 int chisao_get_state(chisao_handle h, int problem, chisao_state *s);
 int chisao_set_state(chisao_handle h, int problem, const chisao_state *s);
 

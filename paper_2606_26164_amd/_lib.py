@@ -45,7 +45,8 @@ class State(C.Structure):
                 ("active", C.c_void_p), ("stuck_pre", C.c_void_p), ("removed", C.c_void_p), ("trace", C.c_void_p),
                 ("k", C.c_int32), ("gr_disabled", C.c_int32), ("gr_fail", C.c_int32), ("gr_used_last", C.c_int32),
                 ("gr_prev_modes", C.c_int32), ("S", C.c_void_p), ("Y", C.c_void_p), ("rho", C.c_void_p),
-                ("head", C.c_void_p), ("cnt", C.c_void_p), ("conv", C.c_void_p), ("Fg", C.c_void_p)]
+                ("head", C.c_void_p), ("cnt", C.c_void_p), ("conv", C.c_void_p), ("Fg", C.c_void_p),
+                ("Wd", C.c_void_p), ("wvalid", C.c_void_p)]
 
 
 class TuningEntry(C.Structure):

@@ -176,15 +176,16 @@ class Optimizer:
         if history:
             out.update(S=np.zeros((N, m, d), np.float32), Y=np.zeros((N, m, d), np.float32),
                        rho=np.zeros((N, m), np.float32), head=np.zeros(N, np.int32), cnt=np.zeros(N, np.int32),
-                       conv=np.zeros(N, np.uint8), Fg=np.zeros(N, np.float32))
-            for f in ("S", "Y", "rho", "head", "cnt", "conv", "Fg"):
+                       conv=np.zeros(N, np.uint8), Fg=np.zeros(N, np.float32), Wd=np.zeros((N, d), np.float32),
+                       wvalid=np.zeros(N, np.uint8))
+            for f in ("S", "Y", "rho", "head", "cnt", "conv", "Fg", "Wd", "wvalid"):
                 setattr(s, f, out[f].ctypes.data)
         L.check(self.lib.chisao_get_state(self.h, problem, C.byref(s)), "chisao_get_state")
         out.update(k=s.k, gr_disabled=s.gr_disabled, gr_fail=s.gr_fail, gr_used_last=s.gr_used_last,
                    gr_prev_modes=s.gr_prev_modes)
         return out
 
-    def set_state(self, X=None, stuck=None, active=None, k=None, gr=None, problem: int = 0):
+    def set_state(self, X=None, stuck=None, active=None, k=None, gr=None, Wd=None, wvalid=None, problem: int = 0):
         sp = self.specs[problem]
         cur = self.get_state(problem=problem)
         keep = []
@@ -201,6 +202,8 @@ class Optimizer:
                     ptr(active, np.uint8, (sp.N,)), None, None, None, cur["k"] if k is None else int(k),
                     gr.get("gr_disabled", cur["gr_disabled"]), gr.get("gr_fail", cur["gr_fail"]),
                     gr.get("gr_used_last", cur["gr_used_last"]), gr.get("gr_prev_modes", cur["gr_prev_modes"]))
+        s.Wd = ptr(Wd, np.float32, (sp.N, sp.d))
+        s.wvalid = ptr(wvalid, np.uint8, (sp.N,))
         L.check(self.lib.chisao_set_state(self.h, problem, C.byref(s)), "chisao_set_state")
 
     def eval(self, X: torch.Tensor, grad_mode: int = L.GRAD_ADJOINT, want_f: bool = True, want_g: bool = True,

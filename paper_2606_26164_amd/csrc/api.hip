@@ -907,6 +907,8 @@ extern "C" int chisao_get_state(chisao_handle h, int problem, chisao_state *s) {
     if (s->cnt) HIP_TRY(hipMemcpy(s->cnt, D.cnt + s0, sizeof(int) * N, hipMemcpyDeviceToHost));
     if (s->conv) HIP_TRY(hipMemcpy(s->conv, D.conv + s0, N, hipMemcpyDeviceToHost));
     if (s->Fg) HIP_TRY(hipMemcpy(s->Fg, D.Fg + s0, sizeof(float) * N, hipMemcpyDeviceToHost));
+    if (s->Wd) HIP_TRY(rows_d2h(s->Wd, D.Wd, 4, d, DS, s0, N));
+    if (s->wvalid) HIP_TRY(hipMemcpy(s->wvalid, D.wvalid + s0, N, hipMemcpyDeviceToHost));
     Ctl c;
     HIP_TRY(hipMemcpy(&c, D.ctl + problem, sizeof c, hipMemcpyDeviceToHost));
     s->k = c.k;
@@ -939,6 +941,8 @@ extern "C" int chisao_set_state(chisao_handle h, int problem, const chisao_state
     }
     if (s->stuck) HIP_TRY(hipMemcpy(D.stuck + s0, s->stuck, N, hipMemcpyHostToDevice));
     if (s->active) HIP_TRY(hipMemcpy(D.active + s0, s->active, N, hipMemcpyHostToDevice));
+    if (s->Wd) HIP_TRY(hipMemcpy2D(D.Wd + s0 * DS, DS * 4, s->Wd, d * 4, d * 4, N, hipMemcpyHostToDevice));
+    if (s->wvalid) HIP_TRY(hipMemcpy(D.wvalid + s0, s->wvalid, N, hipMemcpyHostToDevice));
     Ctl c;
     HIP_TRY(hipMemcpy(&c, D.ctl + problem, sizeof c, hipMemcpyDeviceToHost));
     c.k = s->k;

@@ -403,3 +403,31 @@ def test_mode_widths_of_isotropic_peaks_are_the_variance():
     print(f"\n{len(ms.F)} modes, widths in [{wg.min():.4f}, {wg.max():.4f}]")
     assert len(ms.F) >= 2
     assert np.all(np.abs(wg - 0.5) < 0.05 * 0.5)
+
+
+def test_resume_from_saved_state_continues_bitwise():
+    """Checkpoint and resume: the state read between cycles (positions,
+    masks, cycle count, Golden Rooster state, preserved widths) given to a new
+    handle continues the run exactly as the uninterrupted one."""
+    from paper_2606_26164_amd.api import Optimizer
+
+    prob, cfg, x0 = _many_stuck_case()
+    with Optimizer(prob, cfg, x0) as a:
+        a.cycle(cfg.n_osc)
+        ref = a.get_state()
+        ref_m, ref_w = a.modes(), a.mode_widths()
+    with Optimizer(prob, cfg, x0) as b:
+        b.cycle(2)
+        st = b.get_state(history=True)
+    with Optimizer(prob, cfg, st["X"]) as c:
+        c.set_state(stuck=st["stuck"], active=st["active"], k=st["k"],
+                    gr={f: st[f] for f in ("gr_disabled", "gr_fail", "gr_used_last", "gr_prev_modes")},
+                    Wd=st["Wd"], wvalid=st["wvalid"])
+        c.cycle(cfg.n_osc - 2)
+        got = c.get_state()
+        got_m, got_w = c.modes(), c.mode_widths()
+    for f in ("X", "F", "G", "stuck", "active", "removed"):
+        np.testing.assert_array_equal(got[f], ref[f], err_msg=f)
+    np.testing.assert_array_equal(got_m.X, ref_m.X)
+    np.testing.assert_array_equal(got_w, ref_w)
+    assert len(ref_m.F) > 0
