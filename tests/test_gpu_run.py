@@ -128,3 +128,37 @@ def test_config3_shape_runs_every_phase():
         assert s["sigma"] == pytest.approx(0.1)
         assert s["n_unfrozen"] > 0 and s["alpha_c"] > 0 and s["alpha_a"] > 0
     assert stats[0]["evals"] > 512 * 18
+
+
+def _distinct(X, tol=1e-2):
+    out = []
+    for x in X:
+        if not any(np.max(np.abs(x - y)) < tol for y in out):
+            out.append(x)
+    return len(out)
+
+
+def test_ablation_without_deduplication_saturates_the_population():
+    """The ablation of Sec. 5.6 (Phase 3 off): nothing is removed, so nothing
+    is reseeded, every converged sample stays frozen and the unfrozen
+    population drains; the mode list fills with copies of the first modes.
+    With Phase 3 the list holds each mode once."""
+    import workloads as W
+    from paper_2606_26164_amd.api import Optimizer
+
+    prob = W.mixture_problem(31, 8, 12, 4.0, lam_range=(0.3, 1.0))
+    res = {}
+    for name, mask in (("full", 0x7E), ("no dedup", 0x7E & ~(1 << 3))):
+        cfg = W.RunConfig(N=600, m=6, n_osc=6, n_conv=25, eps_grad=1e-3, grad_mode=1, seed=9, phase_mask=mask)
+        with Optimizer(prob, cfg, W.uniform_population(9, 600, prob.lo, prob.hi)) as opt:
+            st = opt.cycle(cfg.n_osc, stats=True)
+            ms = opt.modes()
+        res[name] = (st, len(ms.F), _distinct(ms.X))
+        print(f"\n{name}: stuck per cycle {[s['n_stuck'] for s in st]}, K_lost {[s['K_lost'] for s in st]}, "
+              f"modes {len(ms.F)} ({res[name][2]} distinct), unfrozen {st[-2]['n_unfrozen']}")
+    st, n, nd = res["no dedup"]
+    assert all(s["K_lost"] == 0 for s in st)
+    assert n >= 10 * nd
+    assert st[-2]["n_unfrozen"] <= 6
+    st, n, nd = res["full"]
+    assert n == nd and any(s["K_lost"] > 0 for s in st)
