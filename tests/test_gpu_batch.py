@@ -157,3 +157,35 @@ def test_autotuned_schedule_changes_timing_only():
         assert (t["order"], t["grid_cap"]) == (0, 8192) and all(ms == 0 for ms in t["ms"])
     for p in range(len(items)):
         _assert_same(out[0][0][p], out[1][0][p], f"problem {p}: tuned vs default schedule")
+
+
+def test_batched_closed_forms_equal_single_bitwise():
+    """Closed forms share the batch with a mixture: value-only and analytic
+    gradients, one noisy and one ray-seeded problem; each problem's state,
+    modes and widths equal those of its own handle bitwise."""
+    from paper_2606_26164_amd.api import Optimizer
+    from paper_2606_26164_amd import _lib as L
+
+    n_osc = 4
+    items = []
+    specs = [("rastrigin", 8, 0, 0.0, 0), ("ackley", 16, 0, 0.0, L.FLAG_RAY_SEEDING), ("styblinski_tang", 5, 1, 0.2, 0),
+             ("trid", 6, 1, 0.0, 0), ("bukin6", 2, 0, 0.0, 0)]
+    for pid, (name, d, gm, sig, fl) in enumerate(specs):
+        p = W.closed_form_problem(name, d, noise_sigma=sig)
+        c = W.RunConfig(N=300 + 50 * pid, m=6, n_osc=n_osc, n_conv=12, M=6, eps_grad=1e-2, grad_mode=gm, seed=3,
+                        problem_id=pid, flags=fl)
+        items.append((p, c, None if fl else W.uniform_population(pid, c.N, p.lo, p.hi)))
+    pm = W.mixture_problem(19, 8, 6, 4.0, lam_range=(0.3, 1.0))
+    cm = W.RunConfig(N=400, m=6, n_osc=n_osc, n_conv=12, eps_grad=1e-3, grad_mode=1, seed=3, problem_id=len(items))
+    items.append((pm, cm, W.uniform_population(9, 400, pm.lo, pm.hi)))
+    with Optimizer.batched(items) as opt:
+        opt.cycle(n_osc)
+        sb = [_state(opt, p) for p in range(len(items))]
+        mb = [opt.modes(p) for p in range(len(items))]
+        wb = [opt.mode_widths(p) for p in range(len(items))]
+    for p, (prob, cfg, x0) in enumerate(items):
+        with Optimizer(prob, cfg, x0) as one:
+            one.cycle(n_osc)
+            _assert_same(sb[p], _state(one), f"problem {p} ({prob.family})")
+            np.testing.assert_array_equal(mb[p].X, one.modes().X)
+            np.testing.assert_array_equal(wb[p], one.mode_widths())

@@ -340,3 +340,28 @@ def test_ray_seeded_runs_recover_the_global_optimum(name, d):
             found += 1
     print(f"\n{name} d={d}: global optimum in {found}/10 runs")
     assert found == 10
+
+
+@pytest.mark.parametrize("name,d,grad_mode", [("rastrigin", 8, 1), ("styblinski_tang", 12, 1),
+                                              ("rastrigin", 6, 0)])
+def test_noisy_closed_form_first_iteration_parity(name, d, grad_mode):
+    """Noise on a closed form goes through the same epilogue as on a
+    mixture: the first L-BFGS iteration with sigma_n = 0.3 (values, trials
+    and, with central differences, the two stencil draws per coordinate
+    with a wide step) matches the oracle's with the same draws."""
+    from paper_2606_26164_amd.api import Optimizer
+
+    prob = W.closed_form_problem(name, d, noise_sigma=0.3)
+    N = 256
+    cfg = W.RunConfig(N=N, m=6, n_osc=3, n_conv=1, grad_mode=grad_mode, eps_grad=1e-3, seed=13,
+                      fd_h=5e-2 if grad_mode == 0 else 0.0)
+    x0 = W.uniform_population(13, N, prob.lo, prob.hi)
+    with Optimizer(prob, cfg, x0) as opt:
+        opt.run_phases(1 << 1)
+        g = opt.get_state()
+    run = O.OracleRun(prob, cfg, x0)
+    rep = run.phase_converge(trace_in=g["trace"], **REPLAY)
+    assert rep.n_hard == 0, rep
+    _rows_close(g["X"], run.X, 2e-3, "X after one noisy iteration")
+    _rows_close(g["F"][:, None], run.F[:, None], 1e-4, "noisy values", floor=10.0)
+    _rows_close(g["G"], run.G, 2e-2, "gradient", floor=10.0)
