@@ -289,7 +289,7 @@ extern "C" int chisao_init_batched(chisao_handle *out, int n_problems, const chi
             const size_t d = pr.d, K = closed ? 0 : pr.K, DP = pad_dim(pr.d);
             ProblemDesc &q = h->pdh[p];
             memset(&q, 0, sizeof q);
-            float *Pfrag = nullptr, *muB = nullptr, *muC = nullptr, *logc2 = nullptr, *lo, *hi;
+            float *Pfrag = nullptr, *muB = nullptr, *logc2 = nullptr, *lo, *hi;
             ALLOC(lo, float, d);
             ALLOC(hi, float, d);
             HIP_GO(hipMemcpyAsync(lo, pr.lo, sizeof(float) * d, hipMemcpyHostToDevice, st));
@@ -299,7 +299,6 @@ extern "C" int chisao_init_batched(chisao_handle *out, int n_problems, const chi
                 float *tw, *tmu, *tprec;
                 ALLOC(Pfrag, float, K * DP * DP);
                 ALLOC(muB, float, K * DP);
-                ALLOC(muC, float, K * DP);
                 ALLOC(logc2, float, K);
                 ALLOC(tw, float, K);
                 ALLOC(tmu, float, K * d);
@@ -307,8 +306,7 @@ extern "C" int chisao_init_batched(chisao_handle *out, int n_problems, const chi
                 HIP_GO(hipMemcpyAsync(tw, pr.log_w, sizeof(float) * K, hipMemcpyHostToDevice, st));
                 HIP_GO(hipMemcpyAsync(tmu, pr.mu, sizeof(float) * K * d, hipMemcpyHostToDevice, st));
                 HIP_GO(hipMemcpyAsync(tprec, pr.prec, sizeof(float) * K * d * d, hipMemcpyHostToDevice, st));
-                HIP_GO(launch_prepare(pr.family, pr.d, (int)DP, pr.K, nu, tw, tmu, tprec, logc2, Pfrag, muB, muC, bad,
-                                      st));
+                HIP_GO(launch_prepare(pr.family, pr.d, (int)DP, pr.K, nu, tw, tmu, tprec, logc2, Pfrag, muB, bad, st));
             }
             q.d = pr.d;
             q.DP = (int)DP;
@@ -318,7 +316,6 @@ extern "C" int chisao_init_batched(chisao_handle *out, int n_problems, const chi
             q.nu_plus_d = nu + (float)pr.d;
             q.Pfrag = Pfrag;
             q.muB = muB;
-            q.muC = muC;
             q.logc2 = logc2;
             q.lo = lo;
             q.hi = hi;

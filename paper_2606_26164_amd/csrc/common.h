@@ -134,7 +134,6 @@ struct ProblemDesc {
     float nu, nu_plus_d;
     const float *Pfrag;  // [K][DP/4][64][DP/16] MFMA A-operand fragments of the precision matrices
     const float *muB;    // [K][4][DP/4]  centre coordinates in B-operand lane order
-    const float *muC;    // [K][4][DP/4]  centre coordinates in accumulator lane order
     const float *logc2;  // [K] log2 of weight times normaliser
     const float *lo, *hi;
     int N, s0;

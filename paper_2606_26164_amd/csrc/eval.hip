@@ -11,12 +11,15 @@
 // gradient: 2 K d^2 MFMA flops per point whether or not the gradient is kept.
 //
 // Work layout: one wave per workgroup, 32 points per wave in two 16-point
-// blocks.  v_mfma_f32_16x16x4f32 computes U^T (DP x 16) = P (DP x DP) *
-// Delta^T (DP x 16): lane l supplies P[16mb + l%16][4ks + l/16] (A operand)
-// and delta[point l%16][4ks + l/16] (B operand), and receives
-// u[point l%16][16mb + 4(l/16) + r], r = 0..3.  Components are streamed; the
-// log-sum-exp runs online in base 2 (one rescale per wave only when some
-// lane's running maximum moves).
+// blocks.  v_mfma_f32_16x16x4f32 computes U^T (DP x 16) = P' (DP x DP) *
+// Delta^T (DP x 16), P' the precision matrix with its rows permuted: lane l
+// supplies P[pi(16mb + l%16)][4ks + l/16] (A operand), pi(16mb + 4a + b) =
+// 4(4mb + b) + a, and delta[point l%16][4ks + l/16] (B operand), and receives
+// u at point l%16 and coordinate pi(16mb + 4(l/16) + r) = 4(4mb + r) + l/16,
+// r = 0..3.  So each lane holds u at the very coordinates it holds delta at,
+// and the quadratic form delta . u needs no second copy of delta.
+// Components are streamed; the log-sum-exp runs online in base 2 (one rescale
+// per wave only when some lane's running maximum moves).
 //
 // The closed-form test functions of Appendix D share the kernel's tiling,
 // point generation and epilogues; their value (and analytic gradient) is a
@@ -432,16 +435,12 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
             __syncthreads();
         } else {
             // ---- operand registers ---------------------------------------------
-            float xB[NB][KS], xC[NB][KS];
+            float xB[NB][KS];
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) {
                 const float *row = s_pts + (nb * 16 + n) * LD;
 #pragma unroll
                 for (int ks = 0; ks < KS; ++ks) xB[nb][ks] = row[4 * ks + g];
-#pragma unroll
-                for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) xC[nb][mb * 4 + r] = row[16 * mb + 4 * g + r];
             }
             float mrun[NB], srun[NB];
             float gacc[NB][GRAD ? KS : 1];
@@ -461,8 +460,7 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
             // come through global-address-space pointers: flat loads would also
             // count against the LDS counter, and the cross-lane reductions of the
             // epilogue would then wait for them.
-            const gfloat *Pfrag = as_global(pd.Pfrag), *muBk = as_global(pd.muB), *muCk = as_global(pd.muC),
-                         *logc2 = as_global(pd.logc2);
+            const gfloat *Pfrag = as_global(pd.Pfrag), *muBk = as_global(pd.muB), *logc2 = as_global(pd.logc2);
             const float nu = pd.nu, nupd = pd.nu_plus_d;
             CompRegs<KS, MB> ra;
             auto load = [&](int k, CompRegs<KS, MB> &r) {
@@ -483,34 +481,31 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
                 for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
                     for (int mb = 0; mb < MB; ++mb) acc[nb][mb] = f32x4{0.f, 0.f, 0.f, 0.f};
+                // delta = x - mu_k in B-operand order; with the rows of P
+                // permuted at init, the accumulator of lane (n, g) holds u at
+                // the same coordinates 4 ks + g, so delta also serves the
+                // quadratic form below
+                float bv[NB][KS];
                 __builtin_amdgcn_s_setprio(1);
 #pragma unroll
                 for (int ks = 0; ks < KS; ++ks) {
 #pragma unroll
                     for (int nb = 0; nb < NB; ++nb) {
-                        const float b = xB[nb][ks] - r.muB[ks];
+                        bv[nb][ks] = xB[nb][ks] - r.muB[ks];
 #pragma unroll
                         for (int mb = 0; mb < MB; ++mb)
-                            acc[nb][mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(r.pa[ks][mb], b, acc[nb][mb], 0, 0, 0);
+                            acc[nb][mb] =
+                                __builtin_amdgcn_mfma_f32_16x16x4f32(r.pa[ks][mb], bv[nb][ks], acc[nb][mb], 0, 0, 0);
                     }
                 }
                 __builtin_amdgcn_s_setprio(0);
-                // centre coordinates in accumulator-lane order, only needed now
-                float muC[KS];
-                const gfloat *mc_p = muCk + ((size_t)k * 4 + g) * KS;
-#pragma unroll
-                for (int i = 0; i < KS; i += 4) {
-                    const f32x4 vc = *reinterpret_cast<const gf32x4 *>(mc_p + i);
-                    muC[i] = vc[0]; muC[i + 1] = vc[1]; muC[i + 2] = vc[2]; muC[i + 3] = vc[3];
-                }
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb) {
                     float q = 0.0f;
 #pragma unroll
                     for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-                        for (int rr = 0; rr < 4; ++rr)
-                            q = fmaf(xC[nb][mb * 4 + rr] - muC[mb * 4 + rr], acc[nb][mb][rr], q);
+                        for (int rr = 0; rr < 4; ++rr) q = fmaf(bv[nb][4 * mb + rr], acc[nb][mb][rr], q);
                     q = rows4_sum(q);
                     float l2, w = 1.0f;
                     if constexpr (FAM == 0) {
@@ -610,7 +605,7 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
 #pragma unroll
                     for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-                        for (int r = 0; r < 4; ++r) s_g[pt * LD + 16 * mb + 4 * g + r] = gacc[nb][mb * 4 + r] * inv;
+                        for (int r = 0; r < 4; ++r) s_g[pt * LD + 4 * (4 * mb + r) + g] = gacc[nb][mb * 4 + r] * inv;
                 }
             }
             __syncthreads();
@@ -764,7 +759,7 @@ hipError_t launch_eval(const EvalArgs &a, int DP, int family, int center, bool f
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(64) void prepare_kernel(int family, int d, int DP, int K, float nu, const float *log_w,
                                                      const float *mu, const float *prec, float *logc2, float *Pfrag,
-                                                     float *muB, float *muC, int *bad) {
+                                                     float *muB, int *bad) {
     const int k = blockIdx.x;
     const int lane = threadIdx.x;
     __shared__ double L[64 * 64];
@@ -805,29 +800,28 @@ __global__ __launch_bounds__(64) void prepare_kernel(int family, int d, int DP, 
         }
         logc2[k] = (float)(((double)log_w[k] + c) * 1.4426950408889634);
     }
-    // fragments: Pfrag[k][ks][lane][mb] = P[16 mb + lane%16][4 ks + lane/16]
+    // fragments with permuted rows: Pfrag[k][ks][lane][mb] = P[pi][4 ks + lane/16],
+    // pi = 4 (4 mb + rho % 4) + rho / 4 for rho = lane % 16
     const int KS = DP / 4, MB = DP / 16;
     for (int ks = 0; ks < KS; ++ks)
         for (int mb = 0; mb < MB; ++mb) {
-            const int row = 16 * mb + (lane & 15), col = 4 * ks + (lane >> 4);
+            const int rho = lane & 15;
+            const int row = 4 * (4 * mb + (rho & 3)) + (rho >> 2), col = 4 * ks + (lane >> 4);
             const float v = (row < d && col < d) ? A[row * d + col] : 0.0f;
             Pfrag[(((size_t)k * KS + ks) * 64 + lane) * MB + mb] = v;
         }
-    // centres: muB[k][g][ks] = mu[4 ks + g]; muC[k][g][4 mb + r] = mu[16 mb + 4 g + r]
+    // centres in B-operand order: muB[k][g][ks] = mu[4 ks + g]
     if (lane < 4 * KS) {
         const int gg = lane / KS, i = lane % KS;
         const int cb = 4 * i + gg;
-        const int cc = 16 * (i / 4) + 4 * gg + (i % 4);
         muB[((size_t)k * 4 + gg) * KS + i] = cb < d ? mu[(size_t)k * d + cb] : 0.0f;
-        muC[((size_t)k * 4 + gg) * KS + i] = cc < d ? mu[(size_t)k * d + cc] : 0.0f;
     }
 }
 
 hipError_t launch_prepare(int family, int d, int DP, int K, float nu, const float *log_w, const float *mu,
-                          const float *prec, float *logc2, float *Pfrag, float *muB, float *muC, int *bad,
-                          hipStream_t st) {
+                          const float *prec, float *logc2, float *Pfrag, float *muB, int *bad, hipStream_t st) {
     hipLaunchKernelGGL(prepare_kernel, dim3(K), dim3(64), 0, st, family, d, DP, K, nu, log_w, mu, prec, logc2,
-                       Pfrag, muB, muC, bad);
+                       Pfrag, muB, bad);
     return hipGetLastError();
 }
 

@@ -46,10 +46,9 @@ hipError_t launch_eval(const EvalArgs &a, int DP, int family, int center, bool f
 
 // Per-component constants: log2 normalisers (float64 Cholesky of each
 // precision matrix) and the fragment layouts of the precision matrices and
-// centres.  Writes D.logc2/Pfrag/muB/muC (device buffers passed as mutable).
+// centres.  Writes D.logc2/Pfrag/muB (device buffers passed as mutable).
 hipError_t launch_prepare(int family, int d, int DP, int K, float nu, const float *log_w, const float *mu,
-                          const float *prec, float *logc2, float *Pfrag, float *muB, float *muC, int *bad,
-                          hipStream_t st);
+                          const float *prec, float *logc2, float *Pfrag, float *muB, int *bad, hipStream_t st);
 
 // Cycle kernels (phases 1-6 and their bookkeeping).
 hipError_t launch_fill_u8(uint8_t *p, uint8_t v, size_t n, hipStream_t st);
