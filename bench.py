@@ -55,14 +55,17 @@ COUNTERS = os.path.join(HERE, "profiles", "eval_kernel_config3_counters.md")
 
 
 def eval_source_digest() -> str:
-    """Digest of the evaluation kernel's sources: hardware-counter figures are
-    only used while the kernel is the one they were taken from."""
+    """Digest of the evaluation kernel's sources, comments and blank space
+    removed: hardware-counter figures are only used while the kernel is the
+    one they were taken from."""
     import hashlib
+    import re
 
     h = hashlib.sha256()
     for f in ("eval.hip", "common.h", "kernels.h"):
-        with open(os.path.join(HERE, "paper_2606_26164_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(HERE, "paper_2606_26164_amd", "csrc", f)) as fh:
+            text = re.sub(r"//[^\n]*", "", fh.read())
+        h.update("\n".join(ln.strip() for ln in text.splitlines() if ln.strip()).encode())
     return h.hexdigest()
 
 

@@ -59,7 +59,7 @@ __device__ __forceinline__ void load_frag(const gfloat *p, float out[MB]) {
 }
 
 // One component's operands in registers: precision-matrix fragments,
-// centre coordinates in B- and accumulator-lane order, log2 weight.
+// centre coordinates in B-operand lane order, log2 weight.
 template <int KS, int MB>
 struct CompRegs {
     float pa[KS][MB];
