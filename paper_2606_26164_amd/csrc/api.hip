@@ -215,6 +215,7 @@ extern "C" int chisao_init_batched(chisao_handle *out, int n_problems, const chi
                                       : std::max(10, (int)ceil(3.0 * log2((double)ps[p].d) - 1e-9));
         ncmax = std::max(ncmax, n_conv[p]);
     }
+    DS = (DS + 3) / 4 * 4;  // row stride: a multiple of four floats (aligned vector row access)
     if (NT * (long)DS * std::max(mmax, Mmax) > (1L << 31) - 1)
         return fail(CHISAO_E_INVAL, "population too large for 32-bit indexing");
     chisao_ctx *h = new (std::nothrow) chisao_ctx();
@@ -439,6 +440,14 @@ extern "C" int chisao_init_batched(chisao_handle *out, int n_problems, const chi
         ALLOC(D.part, double, P * (size_t)D.n_part_blocks * 129);
         ALLOC(D.prof, unsigned long long, kProfClasses);
         HIP_GO(hipMemsetAsync(D.X, 0, sizeof(float) * N * DSz, st));
+        // row arrays start at zero: the L-BFGS kernel reads whole aligned
+        // chunks and relies on the columns past each problem's d being zero
+        HIP_GO(hipMemsetAsync(D.G, 0, sizeof(float) * N * DSz, st));
+        HIP_GO(hipMemsetAsync(D.Xprev, 0, sizeof(float) * N * DSz, st));
+        HIP_GO(hipMemsetAsync(D.Gprev, 0, sizeof(float) * N * DSz, st));
+        HIP_GO(hipMemsetAsync(D.Pd, 0, sizeof(float) * N * DSz, st));
+        HIP_GO(hipMemsetAsync(D.S, 0, sizeof(float) * N * (size_t)mmax * DSz, st));
+        HIP_GO(hipMemsetAsync(D.Y, 0, sizeof(float) * N * (size_t)mmax * DSz, st));
         HIP_GO(hipMemsetAsync(D.Wd, 0, sizeof(float) * N * DSz, st));
         HIP_GO(hipMemsetAsync(D.wvalid, 0, N, st));
         HIP_GO(launch_uniform_init(D, st));

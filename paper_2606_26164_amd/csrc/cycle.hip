@@ -248,15 +248,38 @@ hipError_t launch_build_unfrozen(const Dev &D, hipStream_t st) {
 // ---------------------------------------------------------------------------
 template <int CPL>
 __device__ __forceinline__ void row_load(const float *base, int d, int c0, bool ok, float v[CPL]) {
+    // rows are DS floats apart; with DS a multiple of CPL every chunk that
+    // starts inside the row lies inside it and is aligned, so it is read in
+    // one vector access.  The row arrays are zeroed at creation and no writer
+    // puts anything but zeros past d, so a chunk that straddles d reads zeros
+    // there (a mask here would make every load wait before the next issues).
+    if constexpr (CPL > 1) {
+        if (ok && c0 < d) {
+            if constexpr (CPL == 4) {
+                const float4 w = *reinterpret_cast<const float4 *>(base + c0);
+                v[0] = w.x; v[1] = w.y; v[2] = w.z; v[3] = w.w;
+            } else {
+                const float2 w = *reinterpret_cast<const float2 *>(base + c0);
+                v[0] = w.x; v[1] = w.y;
+            }
+        } else {
 #pragma unroll
-    for (int i = 0; i < CPL; ++i) v[i] = (ok && c0 + i < d) ? base[c0 + i] : 0.0f;
+            for (int i = 0; i < CPL; ++i) v[i] = 0.0f;
+        }
+    } else {
+        v[0] = (ok && c0 < d) ? base[c0] : 0.0f;
+    }
 }
 template <int CPL>
 __device__ __forceinline__ void row_store(float *base, int d, int c0, bool ok, const float v[CPL]) {
-    if (!ok) return;
-#pragma unroll
-    for (int i = 0; i < CPL; ++i)
-        if (c0 + i < d) base[c0 + i] = v[i];
+    if (!ok || c0 >= d) return;
+    if constexpr (CPL == 4) {
+        *reinterpret_cast<float4 *>(base + c0) = make_float4(v[0], v[1], v[2], v[3]);
+    } else if constexpr (CPL == 2) {
+        *reinterpret_cast<float2 *>(base + c0) = make_float2(v[0], v[1]);
+    } else {
+        base[c0] = v[0];
+    }
 }
 template <int CPL>
 __device__ __forceinline__ float row_dot(const float a[CPL], const float b[CPL]) {
