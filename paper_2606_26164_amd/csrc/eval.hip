@@ -337,6 +337,9 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
         }
         __syncthreads();
         // ---- generate the points (zero padded to DP), all waves -------------
+        // rows are read in 16-byte chunks when the row stride and base allow it
+        // (the library's own rows always do; a caller's array may not)
+        const bool vrow = (xs & 3) == 0 && (reinterpret_cast<uintptr_t>(a.X) & 15) == 0;
         for (int e = threadIdx.x; e < PPW * KS; e += blockDim.x) {
             const int pt = e / KS, blk = e % KS, c0 = 4 * blk;
             const int s = s_s[pt];
@@ -352,16 +355,34 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
                                      (kHLC << 24) | ((uint32_t)a.step << 16) | pair, (uint32_t)blk, pd.key0, pd.key1);
                     box_muller4(o, z);
                 }
+                float xr[4] = {0.f, 0.f, 0.f, 0.f}, gr[4] = {0.f, 0.f, 0.f, 0.f}, pr[4] = {0.f, 0.f, 0.f, 0.f};
+                if (c0 < d) {
+                    if (vrow) {
+                        const f32x4 w = *reinterpret_cast<const f32x4 *>(a.X + (size_t)s * xs + c0);
+                        xr[0] = w[0]; xr[1] = w[1]; xr[2] = w[2]; xr[3] = w[3];
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            if (c0 + q < d) xr[q] = a.X[(size_t)s * xs + c0 + q];
+                    }
+                    if constexpr (CENTER == kTrial) {
+                        // the library's rows: stride a multiple of four floats
+                        const f32x4 wg = *reinterpret_cast<const f32x4 *>(D.G + (size_t)s * D.DS + c0);
+                        const f32x4 wp = *reinterpret_cast<const f32x4 *>(D.Pd + (size_t)s * D.DS + c0);
+                        gr[0] = wg[0]; gr[1] = wg[1]; gr[2] = wg[2]; gr[3] = wg[3];
+                        pr[0] = wp[0]; pr[1] = wp[1]; pr[2] = wp[2]; pr[3] = wp[3];
+                    }
+                }
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int c = c0 + q;
                     if (c < d) {
-                        float xv = a.X[(size_t)s * xs + c];
+                        float xv = xr[q];
                         if constexpr (CENTER == kTrial) {
                             const float t = ldexpf(1.0f, -(r0 + ci));
                             x0[q] = xv;
-                            g0[q] = D.G[(size_t)s * D.DS + c];
-                            xv = fminf(fmaxf(xv + t * D.Pd[(size_t)s * D.DS + c], pd.lo[c]), pd.hi[c]);
+                            g0[q] = gr[q];
+                            xv = fminf(fmaxf(xv + t * pr[q], pd.lo[c]), pd.hi[c]);
                             dp += g0[q] * (xv - x0[q]);
                         } else if constexpr (CENTER == kProbe) {
                             const float sgn = (ci & 1) ? -1.0f : 1.0f;
