@@ -80,6 +80,7 @@ struct CompRegs {
 // ---------------------------------------------------------------------------
 constexpr float kTwoPi = 6.283185307179586f;
 constexpr float kInvPi = 0.3183098861837907f;
+constexpr float kInvPi2 = 0.10132118364233778f;  // 1 / pi^2
 
 __device__ __forceinline__ float sign_of(float v) { return (float)((v > 0.0f) - (v < 0.0f)); }
 
@@ -116,7 +117,8 @@ __device__ __forceinline__ void cf_partial(int fam, int d, const float *x, int c
             for (int c = c0; c < d; c += 2) {
                 const float v = x[c];
                 float p20, p19;
-                pow20(sinf((float)(c + 1) * v * v * kInvPi), p20, p19);
+                // sin(i x^2 / pi) = sinpi(i x^2 / pi^2): exact range reduction
+                pow20(sinpif((float)(c + 1) * v * v * kInvPi2), p20, p19);
                 a += sinf(v) * p20;
             }
             break;
@@ -163,10 +165,10 @@ __device__ __forceinline__ float cf_grad(int fam, int d, const float *x, int c, 
         }
         case CHISAO_STYBLINSKI_TANG: return -0.5f * (4.0f * v * v * v - 32.0f * v + 5.0f);
         case CHISAO_MICHALEWICZ: {
-            const float ci = (float)(c + 1), u = ci * v * v * kInvPi;
+            const float ci = (float)(c + 1), un = ci * v * v * kInvPi2;  // u / pi
             float p20, p19;
-            pow20(sinf(u), p20, p19);
-            return cosf(v) * p20 + sinf(v) * 20.0f * p19 * cosf(u) * (2.0f * ci * v * kInvPi);
+            pow20(sinpif(un), p20, p19);
+            return cosf(v) * p20 + sinf(v) * 20.0f * p19 * cospif(un) * (2.0f * ci * v * kInvPi);
         }
         case CHISAO_TRID:
             return -2.0f * (v - 1.0f) + (c > 0 ? x[c - 1] : 0.0f) + (c + 1 < d ? x[c + 1] : 0.0f);
