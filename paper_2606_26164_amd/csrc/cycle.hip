@@ -492,7 +492,7 @@ __global__ void fmax_kernel(Dev D) {
     red[threadIdx.x] = v;
     __syncthreads();
     for (int o = kBlock / 2; o > 0; o >>= 1) {
-        if (threadIdx.x < o) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + o]);
+        if ((int)threadIdx.x < o) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + o]);
         __syncthreads();
     }
     if (threadIdx.x == 0) atomicMax(&D.ctl[p].fmax_ord, float_to_ordered(red[0]));
@@ -612,7 +612,7 @@ __global__ __launch_bounds__(kScanBlock) void dedup_offsets_kernel(Dev D) {
         part[threadIdx.x] = v;
         __syncthreads();
         for (int o = 1; o < kScanBlock; o <<= 1) {
-            const int add = threadIdx.x >= o ? part[threadIdx.x - o] : 0;
+            const int add = (int)threadIdx.x >= o ? part[threadIdx.x - o] : 0;
             __syncthreads();
             part[threadIdx.x] += add;
             __syncthreads();

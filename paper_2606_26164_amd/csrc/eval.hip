@@ -501,7 +501,7 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
                 }
                 r.lc2 = logc2[k];
             };
-            auto step = [&](int k, const CompRegs<KS, MB> &r) {
+            auto step = [&](const CompRegs<KS, MB> &r) {
                 f32x4 acc[NB][MB];
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb)
@@ -576,16 +576,16 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
                     load(kb, ra);
                     for (int k = kb; k < ke; k += 2) {
                         load(min(k + 1, ke - 1), rb);
-                        step(k, ra);
+                        step(ra);
                         if (k + 1 >= ke) break;
                         load(min(k + 2, ke - 1), ra);
-                        step(k + 1, rb);
+                        step(rb);
                     }
                 }
             } else {
                 for (int k = kb; k < ke; ++k) {
                     load(k, ra);
-                    step(k, ra);
+                    step(ra);
                 }
             }
             if constexpr (SPLIT > 1) {
