@@ -365,3 +365,23 @@ def test_noisy_closed_form_first_iteration_parity(name, d, grad_mode):
     _rows_close(g["X"], run.X, 2e-3, "X after one noisy iteration")
     _rows_close(g["F"][:, None], run.F[:, None], 1e-4, "noisy values", floor=10.0)
     _rows_close(g["G"], run.G, 2e-2, "gradient", floor=10.0)
+
+
+def test_autograd_function_on_a_closed_form():
+    """The torch.autograd.Function around the value/gradient kernel works for
+    the closed forms too: backward is the analytic gradient, scaled."""
+    from paper_2606_26164_amd import log_density
+
+    prob = W.closed_form_problem("styblinski_tang", 12)
+    opt = _opt(prob)
+    X = torch.from_numpy(_points("styblinski_tang", prob, 50, 4)).cuda().requires_grad_(True)
+    f = log_density(X, opt)
+    w = torch.linspace(-1, 2, f.shape[0], device=f.device)
+    (f * w).sum().backward()
+    op = O.OracleProblem(prob)
+    Xd = X.detach().cpu().numpy().astype(np.float64)
+    f_or, G_or, sf, sg = _sensitivity(op, Xd)
+    assert np.all(np.abs(f.detach().cpu().numpy() - f_or) <= sf + 16 * U32 * _magnitude("styblinski_tang", Xd))
+    want = w.cpu().numpy()[:, None] * G_or
+    tol = 2 * (sg + 16 * U32 * _grad_magnitude("styblinski_tang", Xd, G_or))
+    assert np.all(np.abs(X.grad.cpu().numpy() - want) <= tol)
