@@ -12,7 +12,7 @@ centres drawn in ``[-a, a]^d``.
 """
 from __future__ import annotations
 
-from dataclasses import dataclass, field, replace
+from dataclasses import dataclass, replace
 from typing import List
 
 import numpy as np
