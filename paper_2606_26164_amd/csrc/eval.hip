@@ -26,6 +26,8 @@
 // sum over coordinates evaluated on the VALU, two lanes per point.
 #include <math.h>
 
+#include <type_traits>
+
 #include "kernels.h"
 
 namespace chisao {
@@ -35,6 +37,8 @@ typedef float f32x2 __attribute__((ext_vector_type(2)));
 
 constexpr int NB = 2;    // 16-point blocks per wave
 constexpr int PPW = 32;  // points per wave
+using AllBlocks = std::integral_constant<int, NB>;
+using OneBlock = std::integral_constant<int, 1>;
 constexpr float kLog2e = 1.4426950408889634f;
 constexpr float kLn2 = 0.6931471805599453f;
 // online log-sum-exp: headroom (log2) a term may exceed the running reference
@@ -202,21 +206,27 @@ __device__ __forceinline__ int centres(const EvalArgs &a, const ProblemDesc &pd)
         default: return 1;
     }
 }
-__device__ __forceinline__ long tiles_of(int count, int V, int &jpw, int &wpj) {
+// tiles of ppw points: jpw jobs per tile, or wpj tiles per job
+__device__ __forceinline__ long tiles_of(int count, int V, int ppw, int &jpw, int &wpj) {
     if (V <= 0 || count <= 0) {
         jpw = 1;
         wpj = 1;
         return 0;
     }
-    if (V <= PPW) {
-        jpw = PPW / V;
+    if (V <= ppw) {
+        jpw = ppw / V;
         wpj = 1;
         return (count + jpw - 1) / jpw;
     }
     jpw = 1;
-    wpj = (V + PPW - 1) / PPW;
+    wpj = (V + ppw - 1) / ppw;
     return (long)count * wpj;
 }
+// Line-search launches of at most this many full tiles run half tiles (16
+// points, one MFMA column block): twice the tiles, each with half the matrix
+// work per component, still one workgroup per CU, so the launch, whose time is
+// one tile's pass over the components, takes about half as long.
+constexpr int kHalfTileMax = 128;
 
 // SPLIT waves share a tile: each contracts a contiguous part of the
 // components and the first (lead) wave merges the partial log-sum-exp states
@@ -242,10 +252,13 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
     __shared__ int s_pass[PPW];
     __shared__ int s_acc[PPW];
     __shared__ int s_pref[kMaxClass + 1];
+    __shared__ int s_ppw;  // points per tile in this launch
     // line search: each point's sample row and gradient before the step, and
     // the partial sums of g . (x_trial - x) over blocks of four coordinates,
     // all gathered while the points are generated
     constexpr bool TRIAL = CENTER == kTrial;
+    // half tiles: only split line-search tiles, whose launches are latency-bound
+    constexpr bool HALF = TRIAL && SPLIT > 1 && !FD;
     __shared__ float s_x0[TRIAL ? PPW * LD : 1];
     __shared__ float s_g0[TRIAL ? PPW * LD : 1];
     __shared__ float s_dp[TRIAL ? PPW * KS : 1];
@@ -266,7 +279,7 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
             const int Vs = FD ? 2 * pd.d : 1;
             const int jobs = job_count(a, p, pd);
             int jpw, wpj;
-            acc += (int)tiles_of(jobs, centres(a, pd) * Vs, jpw, wpj);
+            acc += (int)tiles_of(jobs, centres(a, pd) * Vs, PPW, jpw, wpj);
             s_pref[j + 1] = acc;
             // evaluation counts, once per launch (block 0) rather than per tile
             if (blockIdx.x == 0 && !ext && jobs > 0) {
@@ -276,9 +289,25 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
             }
         }
         if (blockIdx.x == 0 && pts) atomicAdd(&D.prof[FD ? 3 : CENTER], pts);
+        if constexpr (HALF) {
+            int ppw = PPW;
+            if (acc <= kHalfTileMax) {
+                ppw = PPW / 2;
+                acc = 0;
+                for (int j = 0; j < a.n_cls; ++j) {
+                    const int p = a.cls[j];
+                    const ProblemDesc &pd = D.pd[p];
+                    int jpw, wpj;
+                    acc += (int)tiles_of(job_count(a, p, pd), centres(a, pd), ppw, jpw, wpj);
+                    s_pref[j + 1] = acc;
+                }
+            }
+            s_ppw = ppw;
+        }
     }
     __syncthreads();
     const int n_tiles = s_pref[a.n_cls];
+    const int ppw = HALF ? s_ppw : PPW;
 
     // Tile order.  Linear: block b takes tiles b, b + G, ...  XCD-chunked:
     // workgroups are dispatched round-robin over the 8 XCDs, so block b runs on
@@ -313,7 +342,7 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
         const int Vs = FD ? 2 * d : 1;
         const int V = Vc * Vs;
         int jpw, wpj;
-        (void)tiles_of(count, V, jpw, wpj);
+        (void)tiles_of(count, V, ppw, jpw, wpj);
         const uint32_t kcyc = (uint32_t)D.ctl[p].k + 1u;
         const float sigma = (CENTER == kProbe) ? D.ctl[p].sigma : 0.0f;
         const int xs = a.x_stride;
@@ -323,14 +352,14 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
             const int pt = lane;
             int job, v;
             bool valid;
-            if (V <= PPW) {
+            if (V <= ppw) {
                 job = (int)(ltile * jpw) + pt / V;
                 v = pt % V;
                 valid = (pt < jpw * V) && job < count;
             } else {
                 job = (int)(ltile / wpj);
-                v = (int)(ltile % wpj) * PPW + pt;
-                valid = v < V;
+                v = (int)(ltile % wpj) * ppw + pt;
+                valid = pt < ppw && v < V;
             }
             s_s[pt] = valid ? (ext ? job : (lst ? lst[job] : pd.s0 + job)) : -1;
             s_c[pt] = v / Vs;
@@ -501,10 +530,12 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
                 }
                 r.lc2 = logc2[k];
             };
-            auto step = [&](const CompRegs<KS, MB> &r) {
+            // contracts one component for the first NBA column blocks of the tile
+            auto step = [&](const CompRegs<KS, MB> &r, auto nba) {
+                constexpr int NBA = decltype(nba)::value;
                 f32x4 acc[NB][MB];
 #pragma unroll
-                for (int nb = 0; nb < NB; ++nb)
+                for (int nb = 0; nb < NBA; ++nb)
 #pragma unroll
                     for (int mb = 0; mb < MB; ++mb) acc[nb][mb] = f32x4{0.f, 0.f, 0.f, 0.f};
                 // delta = x - mu_k in B-operand order; with the rows of P
@@ -516,7 +547,7 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
 #pragma unroll
                 for (int ks = 0; ks < KS; ++ks) {
 #pragma unroll
-                    for (int nb = 0; nb < NB; ++nb) {
+                    for (int nb = 0; nb < NBA; ++nb) {
                         bv[nb][ks] = xB[nb][ks] - r.muB[ks];
 #pragma unroll
                         for (int mb = 0; mb < MB; ++mb)
@@ -526,7 +557,7 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
                 }
                 __builtin_amdgcn_s_setprio(0);
 #pragma unroll
-                for (int nb = 0; nb < NB; ++nb) {
+                for (int nb = 0; nb < NBA; ++nb) {
                     float q = 0.0f;
 #pragma unroll
                     for (int mb = 0; mb < MB; ++mb)
@@ -576,16 +607,24 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
                     load(kb, ra);
                     for (int k = kb; k < ke; k += 2) {
                         load(min(k + 1, ke - 1), rb);
-                        step(ra);
+                        step(ra, AllBlocks{});
                         if (k + 1 >= ke) break;
                         load(min(k + 2, ke - 1), ra);
-                        step(rb);
+                        step(rb, AllBlocks{});
                     }
                 }
             } else {
-                for (int k = kb; k < ke; ++k) {
-                    load(k, ra);
-                    step(ra);
+                auto run = [&](auto nba) {
+                    for (int k = kb; k < ke; ++k) {
+                        load(k, ra);
+                        step(ra, nba);
+                    }
+                };
+                if constexpr (HALF) {
+                    if (ppw < PPW) run(OneBlock{});
+                    else run(AllBlocks{});
+                } else {
+                    run(AllBlocks{});
                 }
             }
             if constexpr (SPLIT > 1) {
@@ -624,7 +663,7 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
             // ---- results to LDS --------------------------------------------
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) {
-                if (!lead) break;
+                if (!lead || (HALF && nb * 16 >= ppw)) break;
                 const int pt = nb * 16 + n;
                 float f = (mrun[nb] + __log2f(srun[nb])) * kLn2;
                 if (noisy && g == 0 && s_s[pt] >= 0) f += noise_of(pt);
