@@ -206,6 +206,16 @@ __device__ __forceinline__ int centres(const EvalArgs &a, const ProblemDesc &pd)
         default: return 1;
     }
 }
+// inclusive prefix sum over the wave
+__device__ __forceinline__ int wave_scan(int v) {
+    const int l = threadIdx.x % kWave;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int u = __shfl_up(v, o, kWave);
+        if (l >= o) v += u;
+    }
+    return v;
+}
 // tiles of ppw points: jpw jobs per tile, or wpj tiles per job
 __device__ __forceinline__ long tiles_of(int count, int V, int ppw, int &jpw, int &wpj) {
     if (V <= 0 || count <= 0) {
@@ -258,7 +268,9 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
     // all gathered while the points are generated
     constexpr bool TRIAL = CENTER == kTrial;
     // half tiles: only split line-search tiles, whose launches are latency-bound
-    constexpr bool HALF = TRIAL && SPLIT > 1 && !FD;
+    static_assert(!(TRIAL && FD), "line-search trials take no finite differences");
+    constexpr bool HALF = TRIAL && SPLIT > 1;
+    __shared__ int s_pref2[HALF ? kMaxClass + 1 : 1];  // tile prefix in half tiles
     __shared__ float s_x0[TRIAL ? PPW * LD : 1];
     __shared__ float s_g0[TRIAL ? PPW * LD : 1];
     __shared__ float s_dp[TRIAL ? PPW * KS : 1];
@@ -268,8 +280,44 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
     const bool lead = SPLIT == 1 || wv == 0;
     const int g = lane >> 4, n = lane & 15;
     const bool ext = a.ext_n >= 0;
-    // tile prefix over the problems of the class
-    if (threadIdx.x == 0) {
+    // Tile prefix over the problems of the class.  Line-search launches are
+    // short and many, so there the first wave computes it, one problem per
+    // lane: the problems' counts are read in parallel, not one dependent load
+    // after another.  The other launches are long; there one thread walks the
+    // problems (the wave version's extra scalar registers cost the long
+    // launches' component loop more than the walk takes).
+    if constexpr (TRIAL) {
+        if (threadIdx.x < kWave) {
+            int carry = 0, carry2 = 0;
+            if (lane == 0) s_pref[0] = s_pref2[0] = 0;
+            for (int j0 = 0; j0 < a.n_cls; j0 += kWave) {
+                const int j = j0 + lane;
+                int t = 0, t2 = 0;
+                if (j < a.n_cls) {
+                    const int p = a.cls[j];
+                    const ProblemDesc &pd = D.pd[p];
+                    const int jobs = job_count(a, p, pd);
+                    const int V = centres(a, pd);
+                    int jpw, wpj;
+                    t = (int)tiles_of(jobs, V, PPW, jpw, wpj);
+                    if constexpr (HALF) t2 = (int)tiles_of(jobs, V, PPW / 2, jpw, wpj);
+                    // evaluation counts, once per launch (block 0) rather than per tile
+                    if (blockIdx.x == 0 && !ext && jobs > 0) {
+                        atomicAdd(&D.ctl[p].evals, jobs * V);
+                        atomicAdd(&D.prof[CENTER], (unsigned long long)(jobs * V));
+                    }
+                }
+                const int inc = wave_scan(t), inc2 = HALF ? wave_scan(t2) : 0;
+                if (j < a.n_cls) {
+                    s_pref[j + 1] = carry + inc;
+                    if constexpr (HALF) s_pref2[j + 1] = carry2 + inc2;
+                }
+                carry += __shfl(inc, kWave - 1, kWave);
+                if constexpr (HALF) carry2 += __shfl(inc2, kWave - 1, kWave);
+            }
+            if (HALF && lane == 0) s_ppw = carry <= kHalfTileMax ? PPW / 2 : PPW;
+        }
+    } else if (threadIdx.x == 0) {
         int acc = 0;
         unsigned long long pts = 0;
         s_pref[0] = 0;
@@ -289,25 +337,11 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
             }
         }
         if (blockIdx.x == 0 && pts) atomicAdd(&D.prof[FD ? 3 : CENTER], pts);
-        if constexpr (HALF) {
-            int ppw = PPW;
-            if (acc <= kHalfTileMax) {
-                ppw = PPW / 2;
-                acc = 0;
-                for (int j = 0; j < a.n_cls; ++j) {
-                    const int p = a.cls[j];
-                    const ProblemDesc &pd = D.pd[p];
-                    int jpw, wpj;
-                    acc += (int)tiles_of(job_count(a, p, pd), centres(a, pd), ppw, jpw, wpj);
-                    s_pref[j + 1] = acc;
-                }
-            }
-            s_ppw = ppw;
-        }
     }
     __syncthreads();
-    const int n_tiles = s_pref[a.n_cls];
     const int ppw = HALF ? s_ppw : PPW;
+    const int *pref = (HALF && ppw < PPW) ? s_pref2 : s_pref;
+    const int n_tiles = pref[a.n_cls];
 
     // Tile order.  Linear: block b takes tiles b, b + G, ...  XCD-chunked:
     // workgroups are dispatched round-robin over the 8 XCDs, so block b runs on
@@ -329,12 +363,12 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
         int lo_j = 0, hi_j = a.n_cls - 1;
         while (lo_j < hi_j) {
             const int mid = (lo_j + hi_j + 1) >> 1;
-            if (s_pref[mid] <= tile) lo_j = mid;
+            if (pref[mid] <= tile) lo_j = mid;
             else hi_j = mid - 1;
         }
         const int p = a.cls[lo_j];
         const ProblemDesc &pd = D.pd[p];
-        const int ltile = tile - s_pref[lo_j];
+        const int ltile = tile - pref[lo_j];
         const int d = pd.d;
         const int count = job_count(a, p, pd);
         const int Vc = centres(a, pd);
