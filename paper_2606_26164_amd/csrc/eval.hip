@@ -186,11 +186,11 @@ __device__ __forceinline__ float cf_grad(int fam, int d, const float *x, int c, 
 }
 
 constexpr int kMaxClass = 256;  // problems per class (LDS budget: 2 waves per SIMD)
-// waves per line-search tile: at DP = 64 a tile's pass over the components is
-// long enough to be worth splitting; smaller components are cheap per tile
-// and the merge would only add work
+// waves per line-search tile: line-search launches are small, so their time
+// is one tile's pass over the components, which four waves share; the closed
+// forms have no component loop to split
 template <int DP, int FAM>
-constexpr int trial_split() { return DP == 64 && FAM < kFamClosed ? 4 : 1; }
+constexpr int trial_split() { return FAM < kFamClosed ? 4 : 1; }
 
 __device__ __forceinline__ int job_count(const EvalArgs &a, int p, const ProblemDesc &pd) {
     if (a.ext_n >= 0) return a.ext_n;
@@ -636,16 +636,24 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
                 // second register set while this one is contracted (the set is
                 // small at DP <= 32); the prefetch past the end reloads the last
                 // component, which keeps the loop branch-free
-                if (kb < ke) {
-                    CompRegs<KS, MB> rb;
-                    load(kb, ra);
-                    for (int k = kb; k < ke; k += 2) {
-                        load(min(k + 1, ke - 1), rb);
-                        step(ra, AllBlocks{});
-                        if (k + 1 >= ke) break;
-                        load(min(k + 2, ke - 1), ra);
-                        step(rb, AllBlocks{});
+                auto run = [&](auto nba) {
+                    if (kb < ke) {
+                        CompRegs<KS, MB> rb;
+                        load(kb, ra);
+                        for (int k = kb; k < ke; k += 2) {
+                            load(min(k + 1, ke - 1), rb);
+                            step(ra, nba);
+                            if (k + 1 >= ke) break;
+                            load(min(k + 2, ke - 1), ra);
+                            step(rb, nba);
+                        }
                     }
+                };
+                if constexpr (HALF) {
+                    if (ppw < PPW) run(OneBlock{});
+                    else run(AllBlocks{});
+                } else {
+                    run(AllBlocks{});
                 }
             } else {
                 auto run = [&](auto nba) {
