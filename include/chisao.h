@@ -267,10 +267,12 @@ const char *chisao_last_error(void);
 
 /* Evaluation launch schedules chosen at init.  Problems are grouped into
  * classes by (padded d, family, gradient mode); for each class the autotuner
- * times CHISAO_TUNE_VARIANTS schedules on a value+gradient pass over the
- * starting population and keeps the fastest: variant v uses tile order v % 2
- * (0 linear, 1 XCD-chunked) and a grid of 8192 (v < 2) or 1024 workgroups.
- * The schedule changes timing only, never results. */
+ * times CHISAO_TUNE_VARIANTS schedules over the starting population, on a
+ * value + adjoint gradient pass (adjoint classes) or a central-difference
+ * stencil pass (finite-difference classes). It keeps the default (variant 0)
+ * unless another is at least 3% faster than the best so far: variant v uses
+ * tile order v % 2 (0 linear, 1 XCD-chunked) and a grid of 8192 (v < 2) or
+ * 1024 workgroups. The schedule changes timing only, never results. */
 #define CHISAO_TUNE_VARIANTS 4
 typedef struct {
     int32_t padded_d;    /* 16, 32 or 64 */

@@ -151,8 +151,14 @@ def test_autotuned_schedule_changes_timing_only():
     assert sum(t["n_problems"] for t in tuned) == len(items)
     for t in tuned:
         assert all(ms > 0 for ms in t["ms"])
-        best = min(range(L.TUNE_VARIANTS), key=lambda v: t["ms"][v])
+        # the default schedule stays unless another is at least 3% faster than
+        # the best so far
+        best = 0
+        for v in range(1, L.TUNE_VARIANTS):
+            if np.float32(t["ms"][v]) < np.float32(0.97) * np.float32(t["ms"][best]):
+                best = v
         assert (t["order"], t["grid_cap"]) == (best % 2, 8192 if best < 2 else 1024)
+        assert t["ms"][best] <= min(t["ms"]) / 0.97
     for t in fixed:
         assert (t["order"], t["grid_cap"]) == (0, 8192) and all(ms == 0 for ms in t["ms"])
     for p in range(len(items)):
