@@ -51,7 +51,7 @@ def lbfgs_bytes(d: int, steps: int, pairs: int) -> int:
 
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-COUNTERS = os.path.join(HERE, "profiles", "eval_kernel_config3_counters.md")
+COUNTERS = os.path.join(HERE, "profiles", "eval_kernel_gauss128_d64_counters.md")
 
 
 def eval_source_digest() -> str:
@@ -123,7 +123,7 @@ def cpu_baseline(prob, cfg, n_samples):
     dt = time.perf_counter() - t
     si = n_samples * (c.n_conv + c.n_cloud + c.n_anti)
     return dict(value=si / dt, unit="sample-iterations/s", cores=O.num_threads(), kind="oracle",
-                sample=f"config-3 problem (d=64, K=128), {n_samples} samples from a uniform start, one non-final "
+                sample=f"d=64, K=128 Gaussian mixture, {n_samples} samples from a uniform start, one non-final "
                        f"cycle with the analytic gradient, FP64: {si} sample-iterations in {dt:.1f} s")
 
 
@@ -204,7 +204,7 @@ def main(argv=None):
         torch.cuda.synchronize()
         log(f"reference copy: {args.calib_copy_mib} MiB read + {args.calib_copy_mib} MiB written")
         del src, dst
-    prob, cfg, x0 = W.config3(N=args.N)
+    prob, cfg, x0 = W.gauss128_d64(N=args.N)
     si_per_cycle = cfg.N * (cfg.n_conv + cfg.n_cloud + cfg.n_anti)
     log(f"adjoint: N={cfg.N} d={prob.d} K={prob.K} warmup={args.warmup} steps={args.steps}")
     adj = run_gpu(prob, cfg, x0, args.warmup, args.steps)
@@ -251,7 +251,7 @@ def main(argv=None):
 
     batch = None
     if args.batch_steps > 0:
-        items = W.config4()
+        items = W.batch64()
         si = sum(c.N * (c.n_conv + c.n_cloud + c.n_anti) for _, c, _ in items)
         from paper_2606_26164_amd.api import Optimizer
 

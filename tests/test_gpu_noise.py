@@ -101,15 +101,15 @@ def test_noisy_fd_first_iteration_parity():
     _rows_close(g["G"], run.G, 2e-2, "noisy FD gradient", floor=10.0)
 
 
-def test_config5_shape_full_run_modes_are_maxima():
-    """Student-t mixture with unit noise at the config-5 shape (d=32, K=48,
+def test_student48_d32_shape_full_run_modes_are_maxima():
+    """Student-t mixture with unit noise at the student48_d32 shape (d=32, K=48,
     M=32 probes at sigma=0.2, gate over 32 draws), a reduced population and
     schedule: every recovered point is a distinct local maximum of the
     noise-free objective, and the run's gate is self-consistent."""
     from oracle.modes import newton_modes
     from paper_2606_26164_amd.api import Optimizer
 
-    prob, cfg, x0 = W.config5(N=16384, n_osc=40)
+    prob, cfg, x0 = W.student48_d32(N=16384, n_osc=40)
     Xall, Fall = newton_modes(prob, log_delta=None)
     with Optimizer(prob, cfg, x0) as opt:
         stats = opt.cycle(cfg.n_osc, stats=True)

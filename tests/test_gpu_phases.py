@@ -58,7 +58,7 @@ def _rows_close(got, want, rel, what, floor=1.0):
 
 
 PH1 = [
-    ("cfg3-shape", lambda: W.config3(N=256, n_osc=3)),
+    ("cfg3-shape", lambda: W.gauss128_d64(N=256, n_osc=3)),
     ("few wide modes", lambda: (lambda p: (p, W.RunConfig(N=300, m=6, n_osc=3, n_conv=15, eps_grad=1e-3,
                                                           grad_mode=1, seed=5),
                                           W.uniform_population(5, 300, p.lo, p.hi)))(
@@ -96,7 +96,7 @@ def test_lbfgs_single_iteration_parity(grad_mode):
     With central differences this is the only meaningful per-step comparison:
     curvature pairs difference two FP32 finite-difference gradients, whose
     rounding (~1e-3 relative at |f| ~ 1e3) the BFGS update amplifies."""
-    prob, cfg, x0 = W.config2(N=256, n_osc=3) if grad_mode == 0 else W.config3(N=192, n_osc=3)
+    prob, cfg, x0 = W.gauss32_d16(N=256, n_osc=3) if grad_mode == 0 else W.gauss128_d64(N=192, n_osc=3)
     cfg = cfg.with_(grad_mode=grad_mode)
     op = O.OracleProblem(prob)
     for t in (1, 2, 5, cfg.n_conv - 1):

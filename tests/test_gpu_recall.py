@@ -105,35 +105,35 @@ def _run_and_score(prob, cfg, x0, name):
     return recall, not_a_max, band_recall, copies
 
 
-def test_config2_recovers_the_significant_set():
+def test_gauss32_d16_recovers_the_significant_set():
     """d=16, K=32, N=16384, 200 cycles, central differences: all significant
     modes; every recovered point is a maximum.  With FP32 central differences
     the stick-test band reaches 4e-3 here, four times eps_dup, so a maximum
     may come back twice (counted and limited, not forbidden)."""
-    prob, cfg, x0 = W.config2()
-    recall, not_a_max, band_recall, copies = _run_and_score(prob, cfg, x0, "config2 (d=16, K=32, N=16384, FD)")
+    prob, cfg, x0 = W.gauss32_d16()
+    recall, not_a_max, band_recall, copies = _run_and_score(prob, cfg, x0, "gauss32_d16 (d=16, K=32, N=16384, FD)")
     assert not_a_max == 0
     assert copies <= 2
     assert band_recall == 1.0
     assert recall == 1.0
 
 
-def test_config3_recovers_every_maximum_under_its_gate():
+def test_gauss128_d64_recovers_every_maximum_under_its_gate():
     """d=64, K=128, N=65536, 300 cycles, adjoint.  From a uniform start no
     sample lies in the basin of the highest peak (a narrow component), and
     with sigma=0.1 the exploration phases move samples by O(0.1) per step, so
     the method (the FP64 oracle as well, at N=2048) settles on lower maxima;
     the checks are that every recovered point is a local maximum and that the
     set is exactly the maxima inside the gate of the best value found."""
-    prob, cfg, x0 = W.config3()
+    prob, cfg, x0 = W.gauss128_d64()
     recall, not_a_max, band_recall, copies = _run_and_score(prob, cfg, x0,
-                                                            "config3 (d=64, K=128, N=65536, adjoint)")
+                                                            "gauss128_d64 (d=64, K=128, N=65536, adjoint)")
     assert not_a_max == 0 and copies == 0
     assert band_recall == 1.0
 
 
-def test_config3_instance_against_the_oracle():
-    """The config-3 problem at N=2048, 6 cycles, FP64 oracle beside the GPU.
+def test_gauss128_d64_instance_against_the_oracle():
+    """The d=64, K=128 mixture at N=2048, 6 cycles, FP64 oracle beside the GPU.
     The exploration phases amplify rounding differences (the smoothing step
     length times the largest curvature is about 10 here), so after the first
     cycle the two populations fall into partly different basins and their
@@ -145,7 +145,7 @@ def test_config3_instance_against_the_oracle():
     from oracle.modes import newton_modes
     from paper_2606_26164_amd.api import Optimizer
 
-    prob, cfg, x0 = W.config3(N=2048, n_osc=6)
+    prob, cfg, x0 = W.gauss128_d64(N=2048, n_osc=6)
     Xall, Fall = newton_modes(prob, log_delta=None)
     tol_all = _tolerances(prob, Xall, cfg.eps_grad)
     order = np.argsort(-Fall)
@@ -172,7 +172,7 @@ def test_config3_instance_against_the_oracle():
                 assert ranks(Xo) == ranks(ms.X)
 
 
-def test_config4_batch_stuck_points_are_stationary_and_gated():
+def test_batch64_batch_stuck_points_are_stationary_and_gated():
     """The 64-problem batch (d in {2..64}, K in 4..64, N in 1024..16384, 50
     cycles) in one handle.  The stick test (Phase 2) certifies a small
     gradient and the quality gate, not curvature: in low dimension with
@@ -185,7 +185,7 @@ def test_config4_batch_stuck_points_are_stationary_and_gated():
     from oracle.modes import newton_modes, value_grad_hess
     from paper_2606_26164_amd.api import Optimizer
 
-    items = W.config4()
+    items = W.batch64()
     t = time.perf_counter()
     with Optimizer.batched(items) as opt:
         opt.cycle(items[0][1].n_osc)
@@ -216,20 +216,20 @@ def test_config4_batch_stuck_points_are_stationary_and_gated():
         n_pts += len(X)
         sig += int(keep.sum())
         hit += int(round(r * keep.sum()))
-    print(f"\nconfig4: {len(items)} problems in {dt:.1f} s; {n_pts} points recovered: {n_max} distinct maxima, "
+    print(f"\nbatch64: {len(items)} problems in {dt:.1f} s; {n_pts} points recovered: {n_max} distinct maxima, "
           f"{n_saddle} saddles, {n_dup} further copies of a maximum; significant modes recovered {hit}/{sig}")
     assert n_max >= 0.9 * n_pts
 
 
-def test_config5_noisy_student_t_full_run():
-    """Config 5 at full size: d=32 Student-t mixture (K=48, nu=3), unit noise on
+def test_student48_d32_noisy_student_t_full_run():
+    """student48_d32 at full size: d=32 Student-t mixture (K=48, nu=3), unit noise on
     every evaluation, N=131072, 400 cycles, M=32 probes at sigma=0.2, gate over
     32 draws.  Every recovered point is stationary in FP64 and inside its own
     gate; recall of the significant set and the peak error are reported."""
     from oracle.modes import newton_modes, value_grad_hess
     from paper_2606_26164_amd.api import Optimizer
 
-    prob, cfg, x0 = W.config5()
+    prob, cfg, x0 = W.student48_d32()
     Xall, Fall = newton_modes(prob, log_delta=None)
     tol_all = _tolerances(prob, Xall, cfg.eps_grad)
     t = time.perf_counter()
@@ -245,7 +245,7 @@ def test_config5_noisy_student_t_full_run():
     recall, _ = _score(X, Xall[keep], tol_all[keep])
     _, not_a_max = _score(X, Xall, tol_all)
     err = [np.abs(Xall - x).max(1).min() for x in X]
-    print(f"\nconfig5: {len(X)} modes in {dt:.1f} s ({dt / cfg.n_osc * 1e3:.1f} ms/cycle); significant set "
+    print(f"\nstudent48_d32: {len(X)} modes in {dt:.1f} s ({dt / cfg.n_osc * 1e3:.1f} ms/cycle); significant set "
           f"{keep.sum()}, recall {recall:.3f}; points that are no distinct maximum {not_a_max}; "
           f"peak error max {max(err) if err else 0:.2e}; f_max {stats[-1]['f_max']:.3f}")
     print(_report(prob, X, ms.F, Xall, Fall))

@@ -23,10 +23,10 @@ def _match(A, B, tol=1e-3):
     return True
 
 
-def test_config1_mode_set_matches_oracle():
+def test_gauss4_d2_mode_set_matches_oracle():
     from paper_2606_26164_amd.api import Optimizer
 
-    prob, cfg, x0 = W.config1()
+    prob, cfg, x0 = W.gauss4_d2()
     run = O.OracleRun(prob, cfg, x0)  # the configuration's own FP64 finite-difference run
     run.run()
     Xo, Fo, _ = run.modes()
@@ -45,7 +45,7 @@ def test_cycle_past_schedule_is_rejected_and_state_kept():
     from paper_2606_26164_amd import _lib as L
     from paper_2606_26164_amd.api import Optimizer
 
-    prob, cfg, x0 = W.config1(N=32)
+    prob, cfg, x0 = W.gauss4_d2(N=32)
     cfg = cfg.with_(n_osc=2, grad_mode=1, eps_grad=1e-4)
     with Optimizer(prob, cfg, x0) as opt:
         opt.cycle(2)
@@ -62,7 +62,7 @@ def test_modes_capacity_error_reports_count():
     from paper_2606_26164_amd import _lib as L
     from paper_2606_26164_amd.api import Optimizer
 
-    prob, cfg, x0 = W.config1(N=64)
+    prob, cfg, x0 = W.gauss4_d2(N=64)
     cfg = cfg.with_(n_osc=3, grad_mode=1, eps_grad=1e-4)
     with Optimizer(prob, cfg, x0) as opt:
         opt.cycle(3)
@@ -77,7 +77,7 @@ def test_invalid_problems_are_rejected():
     from paper_2606_26164_amd import _lib as L
     from paper_2606_26164_amd.api import Optimizer
 
-    prob, cfg, x0 = W.config1(N=16)
+    prob, cfg, x0 = W.gauss4_d2(N=16)
     bad = W.mixture_problem(0, 2, 4, 5.0, isotropic_var=0.25, dirichlet=None)
     bad.prec = bad.prec.copy()
     bad.prec[0, 0, 1] += 0.5  # not symmetric
@@ -101,7 +101,7 @@ def test_invalid_problems_are_rejected():
 def test_same_seed_same_state_bitwise():
     from paper_2606_26164_amd.api import Optimizer
 
-    prob, cfg, x0 = W.config3(N=256, n_osc=3)
+    prob, cfg, x0 = W.gauss128_d64(N=256, n_osc=3)
     outs = []
     for _ in range(2):
         with Optimizer(prob, cfg, x0) as opt:
@@ -111,12 +111,12 @@ def test_same_seed_same_state_bitwise():
         np.testing.assert_array_equal(outs[0][key], outs[1][key], err_msg=key)
 
 
-def test_config3_shape_runs_every_phase():
+def test_gauss128_d64_shape_runs_every_phase():
     """d=64, K=128 at a small population: every phase executes and the state
     stays inside the box; sample counts are consistent."""
     from paper_2606_26164_amd.api import Optimizer
 
-    prob, cfg, x0 = W.config3(N=512, n_osc=4)
+    prob, cfg, x0 = W.gauss128_d64(N=512, n_osc=4)
     with Optimizer(prob, cfg, x0) as opt:
         stats = opt.cycle(4, stats=True)
         st = opt.get_state()

@@ -540,8 +540,8 @@ def _grid_modes(prob, spacing=4e-3):
     return np.array(out), op.eval(np.array(out), grad=False)
 
 
-def test_config1_modes_match_brute_force_grid():
-    prob, cfg, x0 = W.config1()
+def test_gauss4_d2_modes_match_brute_force_grid():
+    prob, cfg, x0 = W.gauss4_d2()
     run = O.OracleRun(prob, cfg, x0)
     run.run()
     X, F, _ = run.modes()
@@ -557,10 +557,10 @@ def test_config1_modes_match_brute_force_grid():
 
 def test_newton_reference_modes_match_grid_at_d2():
     """The Newton reference used to score recall agrees with the brute-force
-    grid on config 1, and with the oracle's own full run."""
+    grid on gauss4_d2, and with the oracle's own full run."""
     from oracle.modes import newton_modes
 
-    prob, cfg, x0 = W.config1()
+    prob, cfg, x0 = W.gauss4_d2()
     Xn, Fn = newton_modes(prob)
     gm, gf = _grid_modes(prob)
     gm = gm[gf >= gf.max() + np.log(0.1)]

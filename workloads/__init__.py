@@ -20,11 +20,11 @@ from .gen import (
     RunConfig,
     closed_form_box,
     closed_form_problem,
-    config1,
-    config2,
-    config3,
-    config4,
-    config5,
+    gauss4_d2,
+    gauss32_d16,
+    gauss128_d64,
+    batch64,
+    student48_d32,
     mixture_problem,
     two_peak_problem,
     uniform_population,
@@ -45,11 +45,11 @@ __all__ = [
     "RunConfig",
     "closed_form_box",
     "closed_form_problem",
-    "config1",
-    "config2",
-    "config3",
-    "config4",
-    "config5",
+    "gauss4_d2",
+    "gauss32_d16",
+    "gauss128_d64",
+    "batch64",
+    "student48_d32",
     "mixture_problem",
     "two_peak_problem",
     "uniform_population",

@@ -197,7 +197,7 @@ def uniform_population(seed: int, N: int, lo: np.ndarray, hi: np.ndarray) -> np.
 # The benchmark workloads.  Each returns (problem, config, x0).
 # --------------------------------------------------------------------------
 
-def config1(N: int = 256):
+def gauss4_d2(N: int = 256):
     """d=2, four isotropic components of standard deviation 0.5, equal weights,
     centres in [-5,5]^2, population in [-6,6]^2; FP64 finite differences h=1e-5,
     m=5, 50 cycles."""
@@ -207,7 +207,7 @@ def config1(N: int = 256):
     return p, c, uniform_population(0, N, p.lo, p.hi)
 
 
-def config2(N: int = 16384, n_osc: int = 200):
+def gauss32_d16(N: int = 16384, n_osc: int = 200):
     """d=16, 32 anisotropic components (lam in [0.1,1]), centres in [-10,10]^16,
     Dirichlet(5) weights; central differences, m=8, 200 cycles."""
     p = mixture_problem(1, 16, 32, 10.0, lam_range=(0.1, 1.0))
@@ -215,7 +215,7 @@ def config2(N: int = 16384, n_osc: int = 200):
     return p, c, uniform_population(1, N, p.lo, p.hi)
 
 
-def config3(N: int = 65536, n_osc: int = 300, grad_mode: int = 1):
+def gauss128_d64(N: int = 65536, n_osc: int = 300, grad_mode: int = 1):
     """d=64, 128 anisotropic components (lam in [0.05,1]), centres in
     [-20,20]^64; m=10, 300 cycles, n_conv=18, M=16 probes at sigma=0.1."""
     p = mixture_problem(2, 64, 128, 20.0, lam_range=(0.05, 1.0))
@@ -224,9 +224,9 @@ def config3(N: int = 65536, n_osc: int = 300, grad_mode: int = 1):
     return p, c, uniform_population(2, N, p.lo, p.hi)
 
 
-def config4(n_problems: int = 64, seed: int = 3):
+def batch64(n_problems: int = 64, seed: int = 3):
     """64 independent problems: d in {2,4,8,16,32,64}, K in 4..64, N in
-    1024..16384, generated like config 2; m=8, 50 cycles."""
+    1024..16384, generated like gauss32_d16; m=8, 50 cycles."""
     rng = np.random.default_rng(seed)
     out: List = []
     for pid in range(n_problems):
@@ -241,7 +241,7 @@ def config4(n_problems: int = 64, seed: int = 3):
     return out
 
 
-def config5(N: int = 131072, n_osc: int = 400):
+def student48_d32(N: int = 131072, n_osc: int = 400):
     """d=32, 48 Student-t components (nu=3), lam in [0.05,1], centres in
     [-20,20]^32, unit additive noise per evaluation; M=32 probes at sigma=0.2,
     m=10, 400 cycles, n_conv=15."""
