@@ -75,6 +75,30 @@ def test_batched_equals_single_bitwise():
         np.testing.assert_array_equal(modes_b[p].F, m1.F)
 
 
+@pytest.mark.parametrize("d", [16, 64])
+def test_line_search_tile_size_does_not_change_results(d):
+    """Line-search launches of at most 128 full tiles (4096 points) run 16-point
+    tiles. Two problems of 3000 samples each take half tiles on handles of
+    their own, and full tiles in a shared class once their steppers together
+    pass that bound. Every point's arithmetic is the same either way, so the
+    batch matches the single handles bitwise."""
+    from paper_2606_26164_amd.api import Optimizer
+
+    items = []
+    for pid in range(2):
+        prob = W.mixture_problem(40 + pid, d, 16, 10.0, lam_range=(0.1, 1.0))
+        cfg = W.RunConfig(N=3000, m=8, n_osc=2, n_conv=12, M=8, eps_grad=1e-3, grad_mode=1, seed=9,
+                          problem_id=pid)
+        items.append((prob, cfg, W.uniform_population(40 + pid, 3000, prob.lo, prob.hi)))
+    with Optimizer.batched(items) as opt:
+        opt.cycle(2)
+        states_b = [_state(opt, p) for p in range(2)]
+    for p, (prob, cfg, x0) in enumerate(items):
+        with Optimizer(prob, cfg, x0) as one:
+            one.cycle(2)
+            _assert_same(states_b[p], _state(one), f"d={d} problem {p}")
+
+
 @pytest.mark.parametrize("grad_mode", [1, 0])
 def test_graph_replay_equals_eager_bitwise(grad_mode):
     from paper_2606_26164_amd import _lib as L
