@@ -6,6 +6,7 @@ float32 arrays of ``workloads`` widened to float64.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 import os
 import subprocess
@@ -79,34 +80,51 @@ class _Replay(C.Structure):
 _lib = None
 
 
+def _bind(L):
+    """Declare the argument types of the exported functions on a loaded build."""
+    P = C.POINTER
+    L.orc_philox4x32_10.argtypes = [P(C.c_uint32), P(C.c_uint32), P(C.c_uint32)]
+    L.orc_u01.argtypes = [C.c_uint32]
+    L.orc_u01.restype = C.c_double
+    L.orc_prepare.argtypes = [P(_Problem), C.c_void_p]
+    L.orc_eval_batch.argtypes = [P(_Problem), C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]
+    L.orc_fd_grad_batch.argtypes = [P(_Problem), C.c_void_p, C.c_double, C.c_int, C.c_void_p, C.c_void_p]
+    L.orc_two_loop.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
+                               C.c_void_p, C.c_void_p, C.c_void_p]
+    L.orc_householder_q.argtypes = [C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]
+    for name in ("orc_phase_converge", "orc_cycle"):
+        getattr(L, name).argtypes = [P(_Problem), C.c_void_p, P(_Config), P(_State), P(_Replay)]
+    L.orc_lbfgs_iterate.argtypes = [P(_Problem), C.c_void_p, P(_Config), P(_State), C.c_int, C.c_int,
+                                    P(_Replay)]
+    L.orc_phase_stick.argtypes = [P(_Problem), C.c_void_p, P(_Config), P(_State), P(_Replay)]
+    L.orc_phase_dedup.argtypes = [P(_Problem), P(_Config), P(_State), P(_Replay)]
+    L.orc_phase_reseed.argtypes = [P(_Problem), P(_Config), P(_State)]
+    L.orc_phase_hlc.argtypes = [P(_Problem), C.c_void_p, P(_Config), P(_State)]
+    L.orc_phase_anti.argtypes = [P(_Problem), C.c_void_p, P(_Config), P(_State)]
+    L.orc_init_population.argtypes = [P(_Problem), P(_Config), C.c_void_p]
+    L.orc_num_threads.restype = C.c_int
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
-        path = build()
-        L = C.CDLL(path)
-        P = C.POINTER
-        L.orc_philox4x32_10.argtypes = [P(C.c_uint32), P(C.c_uint32), P(C.c_uint32)]
-        L.orc_u01.argtypes = [C.c_uint32]
-        L.orc_u01.restype = C.c_double
-        L.orc_prepare.argtypes = [P(_Problem), C.c_void_p]
-        L.orc_eval_batch.argtypes = [P(_Problem), C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]
-        L.orc_fd_grad_batch.argtypes = [P(_Problem), C.c_void_p, C.c_double, C.c_int, C.c_void_p, C.c_void_p]
-        L.orc_two_loop.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
-                                   C.c_void_p, C.c_void_p, C.c_void_p]
-        L.orc_householder_q.argtypes = [C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]
-        for name in ("orc_phase_converge", "orc_cycle"):
-            getattr(L, name).argtypes = [P(_Problem), C.c_void_p, P(_Config), P(_State), P(_Replay)]
-        L.orc_lbfgs_iterate.argtypes = [P(_Problem), C.c_void_p, P(_Config), P(_State), C.c_int, C.c_int,
-                                        P(_Replay)]
-        L.orc_phase_stick.argtypes = [P(_Problem), C.c_void_p, P(_Config), P(_State), P(_Replay)]
-        L.orc_phase_dedup.argtypes = [P(_Problem), P(_Config), P(_State), P(_Replay)]
-        L.orc_phase_reseed.argtypes = [P(_Problem), P(_Config), P(_State)]
-        L.orc_phase_hlc.argtypes = [P(_Problem), C.c_void_p, P(_Config), P(_State)]
-        L.orc_phase_anti.argtypes = [P(_Problem), C.c_void_p, P(_Config), P(_State)]
-        L.orc_init_population.argtypes = [P(_Problem), P(_Config), C.c_void_p]
-        L.orc_num_threads.restype = C.c_int
-        _lib = L
+        _lib = _bind(C.CDLL(build()))
     return _lib
+
+
+@contextlib.contextmanager
+def using_library(path: str):
+    """Route every oracle call to another build of the oracle for the duration
+    of the block.  Used by the mutation tests, which compile a copy of the
+    source with one planted mistake and check that the pins catch it."""
+    global _lib
+    saved = _lib
+    _lib = _bind(C.CDLL(os.path.abspath(path)))
+    try:
+        yield _lib
+    finally:
+        _lib = saved
 
 
 def _ptr(a: np.ndarray | None):
