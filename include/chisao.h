@@ -60,7 +60,17 @@ extern "C" {
  * of freedom and scale matrix prec_k^-1; or one of the closed-form test
  * functions, for which K, nu, log_w, mu and prec are ignored (the arrays may
  * be NULL) and the box is the caller's (Appendix D gives each function's).
- * All arrays are host memory, copied by chisao_init. */
+ * All arrays are host memory, copied by chisao_init.
+ *
+ * Form of the mixture parameters.  A component is given by its precision
+ * matrix P_k = Sigma_k^-1 and its log weight, not by a whitening factor W_k
+ * (P_k = W_k^T W_k) and a precomputed log normaliser: with u = P_k (x - mu_k)
+ * one matrix product per component yields both the quadratic form
+ * (x - mu_k) . u of the value and the direction -u of the analytic gradient,
+ * where W_k would need a second product W_k^T (W_k (x - mu_k)) for the
+ * gradient.  The library derives each normaliser itself (an FP64 Cholesky
+ * factorisation of P_k at init), so the caller cannot pass one that is
+ * inconsistent with P_k.  A caller holding W_k forms W_k^T W_k. */
 typedef struct {
     int32_t family;      /* CHISAO_GAUSS, CHISAO_STUDENT_T or a closed form CHISAO_RASTRIGIN..CHISAO_BUKIN6 */
     int32_t d;           /* dimension, 1..64 (2 for CHISAO_BUKIN6) */
@@ -82,9 +92,10 @@ typedef struct {
     int32_t N;          /* population size, 1..2^30 */
     int32_t m;          /* L-BFGS memory, 1..32 */
     int32_t n_osc;      /* oscillation cycles */
-    int32_t n_conv;     /* L-BFGS iterations per cycle; auto: max(10, ceil(3 log2 d)) */
-    int32_t n_anti;     /* anti-convergence steps */
-    int32_t n_cloud;    /* Hands Like Clouds steps */
+    int32_t n_conv;     /* L-BFGS iterations per cycle, at most 255; auto: max(10, ceil(3 log2 d)) */
+    int32_t n_anti;     /* anti-convergence steps, 0..255 */
+    int32_t n_cloud;    /* Hands Like Clouds steps, 0..255 (a step index has 8 bits of the random-stream
+                           counter, so longer phases would reuse draws) */
     int32_t M;          /* probes per smoothed gradient, 1..32 */
     float eps_grad;     /* stick threshold on the gradient sup-norm */
     float eps_dup;      /* L-infinity deduplication radius */
@@ -140,7 +151,9 @@ typedef struct {
     float alpha_c;      /* Hands Like Clouds step length */
     float alpha_a;      /* anti-convergence step length */
     int32_t ls_fail;    /* line searches that failed during Phase 1 */
-    int32_t evals;      /* objective evaluations (points) during the cycle */
+    int32_t n_nonfinite;/* samples taken out of use at Phase 2 because their value, gate value or gradient
+                           was not finite (they join no reduction, are never stuck and are not reseeded) */
+    int64_t evals;      /* objective evaluations (points) during the cycle */
 } chisao_cycle_stats;
 
 /* Host view of the population state for chisao_get_state / chisao_set_state.
@@ -237,6 +250,10 @@ int chisao_mode_widths(chisao_handle h, int problem, float *w_out, int cap, int 
 /* Copy the state to / from host memory (synchronizes).  set_state writes X,
  * stuck, active, k, the Golden Rooster state and the preserved widths; F, G,
  * the histories and the decision arrays are recomputed by the next cycle.
+ * Every coordinate of X must lie in the box or be NaN; a NaN row stands for a
+ * sample whose objective cannot be evaluated, and like any sample whose
+ * value or gradient is not finite after Phase 1 it is taken out of use at
+ * Phase 2 (counted in chisao_cycle_stats.n_nonfinite).
  * Between cycles this is the whole state a run carries forward: a handle
  * given it continues exactly as the handle it was read from. */
 int chisao_get_state(chisao_handle h, int problem, chisao_state *s);

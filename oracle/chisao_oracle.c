@@ -86,6 +86,7 @@ typedef struct {
     double *Fg; /* quality-gate values (noisy objectives only) */
     double *W;       /* N*d preserved inverse-Hessian diagonals (width export), or NULL */
     uint8_t *wvalid; /* N: W holds a value */
+    int32_t n_nonfinite; /* samples deactivated by the non-finite guard of the last Phase 2 */
 } orc_state;
 
 typedef struct {
@@ -869,6 +870,20 @@ int orc_phase_stick(const orc_problem *P, const double *logc, const orc_config *
         if (rc) return rc;
     }
     const double *Fv = gate_values(P, S);
+    /* A sample whose value, gate value or gradient is not finite leaves the
+     * population here, before f_max and every later reduction over samples
+     * (the paper is silent on non-finite evaluations; reading). */
+    int nbad = 0;
+    for (int i = 0; i < N; ++i) {
+        if (!S->active[i]) continue;
+        int ok = isfinite(S->F[i]) && isfinite(Fv[i]);
+        for (int l = 0; ok && l < d; ++l) ok = isfinite(S->G[(size_t)i * d + l]);
+        if (!ok) {
+            S->active[i] = 0;
+            ++nbad;
+        }
+    }
+    S->n_nonfinite = nbad;
     double fmax_ = -INFINITY;
     for (int i = 0; i < N; ++i)
         if (S->active[i] && Fv[i] > fmax_) fmax_ = Fv[i];

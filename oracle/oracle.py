@@ -65,7 +65,7 @@ class _State(C.Structure):
                 ("sigma", C.c_double), ("alpha_c", C.c_double), ("alpha_a", C.c_double),
                 ("K_lost", C.c_int32), ("n_stuck", C.c_int32), ("n_modes", C.c_int32),
                 ("reseed_kind", C.c_int32), ("n_free", C.c_int32), ("n_unfrozen", C.c_int32),
-                ("Fg", C.c_void_p), ("W", C.c_void_p), ("wvalid", C.c_void_p)]
+                ("Fg", C.c_void_p), ("W", C.c_void_p), ("wvalid", C.c_void_p), ("n_nonfinite", C.c_int32)]
 
 
 class _Replay(C.Structure):
@@ -343,7 +343,8 @@ class OracleRun:
         s = self.st
         return dict(k=s.k, f_max=s.f_max, sigma=s.sigma, alpha_c=s.alpha_c, alpha_a=s.alpha_a, K_lost=s.K_lost,
                     n_stuck=s.n_stuck, n_modes=s.n_modes, reseed_kind=s.reseed_kind, n_free=s.n_free,
-                    n_unfrozen=s.n_unfrozen, gr_disabled=s.gr_disabled, gr_fail=s.gr_fail)
+                    n_unfrozen=s.n_unfrozen, gr_disabled=s.gr_disabled, gr_fail=s.gr_fail,
+                    n_nonfinite=s.n_nonfinite)
 
 
 def two_loop(g, S, Y, rho, cnt, head):

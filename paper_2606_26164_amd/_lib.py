@@ -37,7 +37,8 @@ class CycleStats(C.Structure):
     _fields_ = [("k", C.c_int32), ("f_max", C.c_float), ("n_stuck", C.c_int32), ("K_lost", C.c_int32),
                 ("n_modes", C.c_int32), ("reseed_kind", C.c_int32), ("n_free", C.c_int32),
                 ("n_unfrozen", C.c_int32), ("n_active", C.c_int32), ("sigma", C.c_float), ("alpha_c", C.c_float),
-                ("alpha_a", C.c_float), ("ls_fail", C.c_int32), ("evals", C.c_int32)]
+                ("alpha_a", C.c_float), ("ls_fail", C.c_int32), ("n_nonfinite", C.c_int32),
+                ("evals", C.c_int64)]
 
 
 class State(C.Structure):

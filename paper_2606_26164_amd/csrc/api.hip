@@ -175,6 +175,9 @@ static int validate(const chisao_problem *p, const chisao_config *c, int idx) {
     if (c->m < 1 || c->m > 32) return fail(CHISAO_E_INVAL, "problem %d: m must be in 1..32", idx);
     if (c->n_osc < 1) return fail(CHISAO_E_INVAL, "problem %d: n_osc must be >= 1", idx);
     if (c->n_anti < 0 || c->n_cloud < 0) return fail(CHISAO_E_INVAL, "problem %d: negative step count", idx);
+    // the step index occupies bits 16..23 of a random-stream counter word
+    if (c->n_conv > 255 || c->n_anti > 255 || c->n_cloud > 255)
+        return fail(CHISAO_E_INVAL, "problem %d: n_conv, n_anti and n_cloud must be at most 255", idx);
     if (c->M < 1 || c->M > 32) return fail(CHISAO_E_INVAL, "problem %d: M must be in 1..32", idx);
     if (c->ls_max < 1 || c->ls_max > 15) return fail(CHISAO_E_INVAL, "problem %d: ls_max must be in 1..15", idx);
     if (c->grad_mode != CHISAO_GRAD_FD && c->grad_mode != CHISAO_GRAD_ADJOINT)
@@ -864,7 +867,8 @@ extern "C" int chisao_cycle(chisao_handle h, int n_cycles, chisao_cycle_stats *s
                 o.alpha_c = r.alpha_c;
                 o.alpha_a = r.alpha_a;
                 o.ls_fail = r.ls_fail;
-                o.evals = r.evals;
+                o.n_nonfinite = r.n_nonfinite;
+                o.evals = (int64_t)r.evals;
             }
     }
     return CHISAO_OK;
@@ -946,8 +950,10 @@ extern "C" int chisao_set_state(chisao_handle h, int problem, const chisao_state
         std::vector<float> lo(d), hi(d);
         HIP_TRY(hipMemcpy(lo.data(), q.lo, sizeof(float) * d, hipMemcpyDeviceToHost));
         HIP_TRY(hipMemcpy(hi.data(), q.hi, sizeof(float) * d, hipMemcpyDeviceToHost));
+        // NaN marks a sample whose objective cannot be evaluated (it leaves the
+        // population at the next Phase 2); anything else must lie in the box
         for (size_t i = 0; i < N * d; ++i)
-            if (!(s->X[i] >= lo[i % d] && s->X[i] <= hi[i % d]))
+            if (!(isnan(s->X[i]) || (s->X[i] >= lo[i % d] && s->X[i] <= hi[i % d])))
                 return fail(CHISAO_E_INVAL, "sample %zu lies outside the box", i / d);
         HIP_TRY(hipMemcpy2D(D.X + s0 * DS, DS * 4, s->X, d * 4, d * 4, N, hipMemcpyHostToDevice));
     }

@@ -165,7 +165,8 @@ struct Ctl {
     int reseed_kind;  // 0 none, 1 RM, 2 GR, 3 deactivate
     int gr_disabled, gr_fail, gr_used_last, gr_prev_modes;
     int ls_fail;
-    int evals;
+    int n_nonfinite;  // samples deactivated by the non-finite guard of Phase 2
+    unsigned long long evals;
     float f_max, sigma, alpha_c, alpha_a;
 };
 
@@ -175,7 +176,8 @@ struct CycleRecord {
     float f_max;
     int n_stuck, K_lost, n_modes, reseed_kind, n_free, n_unfrozen, n_active;
     float sigma, alpha_c, alpha_a;
-    int ls_fail, evals;
+    int ls_fail, n_nonfinite;
+    unsigned long long evals;
 };
 
 // Status bytes written by the line-search epilogue.

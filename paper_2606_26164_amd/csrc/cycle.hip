@@ -92,6 +92,7 @@ __global__ void begin_ctl_kernel(Dev D) {
     c->n_stuck = c->K_lost = c->n_modes = c->n_active = 0;
     c->reseed_kind = 0;
     c->ls_fail = 0;
+    c->n_nonfinite = 0;
     c->evals = 0;
     c->f_max = -INFINITY;
     c->sigma = c->alpha_c = c->alpha_a = 0.0f;
@@ -480,6 +481,15 @@ __global__ void stick_reset_kernel(Dev D) {
     D.ctl[p].fmax_ord = float_to_ordered(-INFINITY);
 }
 
+// A sample whose value, gate value or gradient is not finite leaves the
+// population here, before f_max and every later reduction over samples.
+__device__ __forceinline__ bool sample_finite(const Dev &D, const ProblemDesc &pd, int s) {
+    bool ok = isfinite(D.F[s]) && isfinite(gate_values(D, pd)[s]);
+    const float *g = D.G + (size_t)s * D.DS;
+    for (int c = 0; c < pd.d; ++c) ok = ok && isfinite(g[c]);
+    return ok;
+}
+
 __global__ void fmax_kernel(Dev D) {
     __shared__ float red[kBlock];
     const int p = blockIdx.y;
@@ -487,7 +497,13 @@ __global__ void fmax_kernel(Dev D) {
     float v = -INFINITY;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < pd.N; i += gridDim.x * blockDim.x) {
         const int s = pd.s0 + i;
-        if (D.active[s]) v = fmaxf(v, gate_values(D, pd)[s]);
+        if (!D.active[s]) continue;
+        if (sample_finite(D, pd, s)) {
+            v = fmaxf(v, gate_values(D, pd)[s]);
+        } else {
+            D.active[s] = 0;
+            atomicAdd(&D.ctl[p].n_nonfinite, 1);
+        }
     }
     red[threadIdx.x] = v;
     __syncthreads();
@@ -1306,6 +1322,7 @@ __global__ void end_cycle_kernel(Dev D, int advance) {
         r.alpha_c = c->alpha_c;
         r.alpha_a = c->alpha_a;
         r.ls_fail = c->ls_fail;
+        r.n_nonfinite = c->n_nonfinite;
         r.evals = c->evals;
     }
     if (advance) c->k = k + 1;

@@ -303,8 +303,9 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
                     if constexpr (HALF) t2 = (int)tiles_of(jobs, V, PPW / 2, jpw, wpj);
                     // evaluation counts, once per launch (block 0) rather than per tile
                     if (blockIdx.x == 0 && !ext && jobs > 0) {
-                        atomicAdd(&D.ctl[p].evals, jobs * V);
-                        atomicAdd(&D.prof[CENTER], (unsigned long long)(jobs * V));
+                        const unsigned long long nv = (unsigned long long)jobs * (unsigned long long)V;
+                        atomicAdd(&D.ctl[p].evals, nv);
+                        atomicAdd(&D.prof[CENTER], nv);
                     }
                 }
                 const int inc = wave_scan(t), inc2 = HALF ? wave_scan(t2) : 0;
@@ -331,9 +332,9 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
             s_pref[j + 1] = acc;
             // evaluation counts, once per launch (block 0) rather than per tile
             if (blockIdx.x == 0 && !ext && jobs > 0) {
-                const int nv = jobs * centres(a, pd) * Vs;
+                const unsigned long long nv = (unsigned long long)jobs * centres(a, pd) * Vs;
                 atomicAdd(&D.ctl[p].evals, nv);
-                pts += (unsigned long long)nv;
+                pts += nv;
             }
         }
         if (blockIdx.x == 0 && pts) atomicAdd(&D.prof[FD ? 3 : CENTER], pts);

@@ -162,3 +162,56 @@ def test_ablation_without_deduplication_saturates_the_population():
     assert st[-2]["n_unfrozen"] <= 6
     st, n, nd = res["full"]
     assert n == nd and any(s["K_lost"] > 0 for s in st)
+
+
+def test_non_finite_sample_is_taken_out_of_use():
+    """A NaN row given through set_state is deactivated at Phase 2 and
+    counted; every other sample then ends the run bitwise as in a handle where
+    that slot was inactive from the start (the guard keeps it out of f_max,
+    the smoothing scale, the step lengths and the reseeding lists).  The FP64
+    oracle does the same (test_non_finite_sample_equals_an_empty_slot)."""
+    from paper_2606_26164_amd.api import Optimizer
+
+    prob = W.mixture_problem(3, 16, 12, 4.0, lam_range=(0.3, 1.0))
+    cfg = W.RunConfig(N=700, m=6, n_osc=3, n_conv=14, M=8, eps_grad=1e-3, grad_mode=1, seed=5)
+    x0 = W.uniform_population(4, 700, prob.lo, prob.hi)
+    bad = 301
+    out = []
+    for variant in ("nan", "inactive"):
+        with Optimizer(prob, cfg, x0) as opt:
+            if variant == "nan":
+                X = x0.copy()
+                X[bad] = np.nan
+                opt.set_state(X=X)
+            else:
+                act = np.ones(700, np.uint8)
+                act[bad] = 0
+                opt.set_state(active=act)
+            stats = opt.cycle(3, stats=True)
+            out.append((stats, opt.get_state(), opt.modes()))
+    (s_nan, st_nan, m_nan), (s_off, st_off, m_off) = out
+    assert [s["n_nonfinite"] for s in s_nan] == [1, 0, 0]
+    assert all(s["n_nonfinite"] == 0 for s in s_off)
+    assert st_nan["active"][bad] == 0 and st_nan["stuck"][bad] == 0
+    keep = np.arange(700) != bad
+    np.testing.assert_array_equal(st_nan["X"][keep], st_off["X"][keep])
+    np.testing.assert_array_equal(st_nan["active"], st_off["active"])
+    np.testing.assert_array_equal(st_nan["stuck"], st_off["stuck"])
+    for a, b in zip(s_nan, s_off):
+        assert np.isfinite(a["sigma"]) and a["sigma"] == b["sigma"] and a["alpha_a"] == b["alpha_a"]
+        assert a["f_max"] == b["f_max"] and a["n_modes"] == b["n_modes"]
+    np.testing.assert_array_equal(m_nan.X, m_off.X)
+
+
+def test_step_counts_above_the_counter_field_are_rejected():
+    """The step index has 8 bits of a random-stream counter word."""
+    from paper_2606_26164_amd import _lib as L
+    from paper_2606_26164_amd.api import Optimizer
+
+    prob, cfg, x0 = W.gauss4_d2(N=16)
+    for field in ("n_conv", "n_cloud", "n_anti"):
+        with pytest.raises(L.ChisaoError) as ei:
+            Optimizer(prob, cfg.with_(**{field: 256}), x0)
+        assert ei.value.code == L.E_INVAL
+    with Optimizer(prob, cfg.with_(n_conv=255, n_cloud=255, n_anti=255, n_osc=1), x0):
+        pass

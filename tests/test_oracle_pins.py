@@ -267,6 +267,48 @@ def test_stick_gate():
     assert run.st.f_max == 0.0
 
 
+def test_stick_deactivates_non_finite_samples():
+    """Reading: a sample whose value or gradient is not finite leaves the
+    population at Phase 2, before f_max; the rest of the phase is the
+    brute-force definition over the remaining samples."""
+    X = np.zeros((6, 2))
+    F = np.array([0.0, np.nan, -0.5, np.inf, -1.0, -3.0])
+    G = np.zeros((6, 2))
+    G[2, 1] = np.inf
+    G[4, 0] = -np.nan
+    run = _manual_run(X, F, G)
+    run.phase_stick()
+    assert run.active.tolist() == [1, 0, 0, 0, 0, 1]
+    assert run.st.n_nonfinite == 4
+    assert run.st.f_max == 0.0  # +inf no longer dominates
+    assert run.stuck.tolist() == [1, 0, 0, 0, 0, 0]  # -3 is below the gate 0 + log 0.1
+
+
+def test_non_finite_sample_equals_an_empty_slot():
+    """A whole cycle with one NaN row ends, for every other sample, exactly as
+    a cycle in which that slot was inactive from the start: the guard keeps
+    it out of every reduction (f_max, the smoothing scale, the step lengths,
+    the reseeding lists)."""
+    prob = W.mixture_problem(3, 4, 6, 3.0, lam_range=(0.3, 1.0))
+    cfg = W.RunConfig(N=64, m=4, n_conv=8, M=4, eps_grad=1e-6, seed=5)
+    x0 = W.uniform_population(4, 64, prob.lo, prob.hi).astype(np.float64)
+    bad = 17
+    a = O.OracleRun(prob, cfg, x0)
+    a.X[bad] = np.nan
+    b = O.OracleRun(prob, cfg, x0)
+    b.active[bad] = 0
+    for _ in range(2):
+        a.cycle()
+        b.cycle()
+    keep = np.arange(64) != bad
+    assert a.active[bad] == 0
+    np.testing.assert_array_equal(a.X[keep], b.X[keep])
+    np.testing.assert_array_equal(a.stuck, b.stuck)
+    np.testing.assert_array_equal(a.active, b.active)
+    assert np.isfinite(a.st.sigma) and a.st.sigma == b.st.sigma
+    assert a.st.alpha_a == b.st.alpha_a
+
+
 def test_dedup_ties_chains_and_clusters():
     eps = 1e-3
     X = np.array([
