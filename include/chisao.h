@@ -272,6 +272,28 @@ int chisao_run_phases(chisao_handle h, uint32_t phase_mask);
 int chisao_eval(chisao_handle h, int problem, const float *X_dev, int B, float *f_dev, float *G_dev,
                 int grad_mode);
 
+/* For callers that cannot allocate device memory (serving loops and
+ * harnesses that forbid hipMalloc): chisao_eval without a handle.  The
+ * problem p (host arrays, as for chisao_init) and the finite-difference step
+ * fd_h (<= 0: h_j = 2^-8 max(1, |x_j|), as in chisao_config) replace the
+ * handle; X_dev, f_dev, G_dev and grad_mode are as for chisao_eval, and the
+ * results are bitwise those of chisao_eval on a handle created for p with
+ * that fd_h.  Nothing is allocated: the problem's tables (precision-matrix
+ * fragments, centres, log normalisers, descriptors) are built in a static
+ * device array of 8 MiB that each GPU holds from library load to process
+ * exit.  The tables take 4 (K (DP^2 + d^2 + DP + d + 2) + 2 d) bytes plus
+ * about 1 KiB, DP = d rounded up to 16, 32 or 64: up to K = 251 components at
+ * d = 64; a larger problem fails with CHISAO_E_RANGE and runs nothing.
+ * Enqueued on hip_stream (NULL = default stream) of the current device.  The
+ * call synchronizes that stream once, after uploading the problem (a matrix
+ * that is not positive definite fails with CHISAO_E_INVAL), and returns with
+ * the evaluation kernels enqueued.  Every call on a GPU reuses that GPU's
+ * array: calls on one stream are ordered and safe, but calls whose work
+ * overlaps on one GPU (other threads, other streams) race on the tables and
+ * must be serialized by the caller. */
+int chisao_eval_static(const chisao_problem *p, float fd_h, const float *X_dev, int B, float *f_dev, float *G_dev,
+                       int grad_mode, void *hip_stream);
+
 /* enable = 1: clear the counters and start recording; enable = 0: stop,
  * synchronize and write CHISAO_PROF_CLASSES entries to out (may be NULL). */
 int chisao_profile(chisao_handle h, int enable, chisao_kernel_profile *out);

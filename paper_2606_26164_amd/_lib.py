@@ -65,7 +65,7 @@ PROF_NAMES = ("eval_direct", "eval_trial", "eval_probe", "eval_fd", "lbfgs", "lb
 
 EXPORTS = ("chisao_init", "chisao_init_batched", "chisao_profile", "chisao_cycle", "chisao_modes",
            "chisao_mode_widths", "chisao_get_state", "chisao_set_state", "chisao_run_phases", "chisao_eval",
-           "chisao_destroy", "chisao_last_error", "chisao_tuning")
+           "chisao_destroy", "chisao_last_error", "chisao_tuning", "chisao_eval_static")
 
 _lib = None
 
@@ -97,6 +97,9 @@ def load(path: str = LIB_PATH):
     L.chisao_run_phases.restype = C.c_int
     L.chisao_eval.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int]
     L.chisao_eval.restype = C.c_int
+    L.chisao_eval_static.argtypes = [P(Problem), C.c_float, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int,
+                                     C.c_void_p]
+    L.chisao_eval_static.restype = C.c_int
     L.chisao_profile.argtypes = [C.c_void_p, C.c_int, P(KernelProfile)]
     L.chisao_profile.restype = C.c_int
     L.chisao_destroy.argtypes = [C.c_void_p]

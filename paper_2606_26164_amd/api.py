@@ -25,19 +25,25 @@ class ModeSet:
     F: np.ndarray
 
 
+def _problem_struct(problem):
+    """A ``chisao_problem`` for ``problem`` and the host arrays it points to
+    (which must stay alive while the struct is used)."""
+    d, K = int(problem.d), int(problem.K)
+    keep = dict(log_w=_f32(problem.log_w, (K,)), mu=_f32(problem.mu, (K, d)), prec=_f32(problem.prec, (K, d, d)),
+                lo=_f32(problem.lo, (d,)), hi=_f32(problem.hi, (d,)))
+    cp = L.Problem(int(problem.family), d, K, float(getattr(problem, "nu", 0.0)), keep["log_w"].ctypes.data,
+                   keep["mu"].ctypes.data, keep["prec"].ctypes.data, keep["lo"].ctypes.data, keep["hi"].ctypes.data,
+                   float(getattr(problem, "noise_sigma", 0.0)))
+    return cp, keep
+
+
 class _Spec:
     """Host copies of one problem's arrays, kept alive while the handle is created."""
 
     def __init__(self, problem, config):
         d, K = int(problem.d), int(problem.K)
         self.d, self.K, self.N, self.m = d, K, int(config.N), int(config.m)
-        self.keep = dict(
-            log_w=_f32(problem.log_w, (K,)), mu=_f32(problem.mu, (K, d)), prec=_f32(problem.prec, (K, d, d)),
-            lo=_f32(problem.lo, (d,)), hi=_f32(problem.hi, (d,)))
-        k = self.keep
-        self.cp = L.Problem(int(problem.family), d, K, float(getattr(problem, "nu", 0.0)), k["log_w"].ctypes.data,
-                            k["mu"].ctypes.data, k["prec"].ctypes.data, k["lo"].ctypes.data, k["hi"].ctypes.data,
-                            float(getattr(problem, "noise_sigma", 0.0)))
+        self.cp, self.keep = _problem_struct(problem)
         c = config
         self.cc = L.Config(int(c.N), int(c.m), int(c.n_osc), int(c.n_conv), int(c.n_anti), int(c.n_cloud), int(c.M),
                            float(c.eps_grad), float(c.eps_dup), float(c.log_delta), float(c.momentum),
@@ -218,3 +224,25 @@ class Optimizer:
             L.check(self.lib.chisao_eval(self.h, problem, X.data_ptr(), B, f.data_ptr() if f is not None else None,
                                          G.data_ptr() if G is not None else None, grad_mode), "chisao_eval")
         return f, G
+
+
+def eval_static(problem, X: torch.Tensor, grad_mode: int = L.GRAD_ADJOINT, fd_h: float = 0.0, want_f: bool = True,
+                want_g: bool = True, stream=None):
+    """Objective (and gradient) of ``problem`` at the rows of X (a float32 CUDA
+    tensor) without a handle: ``chisao_eval_static``, which allocates no device
+    memory (the problem's tables go to the library's static device array)."""
+    lib = L.load()
+    cp, keep = _problem_struct(problem)
+    d = int(problem.d)
+    X = X.to(torch.float32).contiguous().reshape(-1, d)
+    B = X.shape[0]
+    f = torch.empty(B, device=X.device, dtype=torch.float32) if want_f else None
+    G = torch.empty(B, d, device=X.device, dtype=torch.float32) if want_g else None
+    st = stream if stream is not None else torch.cuda.current_stream(X.device)
+    with torch.cuda.device(X.device):
+        L.check(lib.chisao_eval_static(C.byref(cp), float(fd_h), X.data_ptr(), B,
+                                       f.data_ptr() if f is not None else None,
+                                       G.data_ptr() if G is not None else None, grad_mode, st.cuda_stream),
+                "chisao_eval_static")
+    del keep  # the call synchronized after copying the problem
+    return f, G

@@ -13,6 +13,7 @@
 
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <tuple>
@@ -140,8 +141,8 @@ static hipError_t timed(chisao_ctx *h, int cls, F &&launch) {
 // ---------------------------------------------------------------------------
 // Validation
 // ---------------------------------------------------------------------------
-static int validate(const chisao_problem *p, const chisao_config *c, int idx) {
-    if (!p || !c) return fail(CHISAO_E_INVAL, "null problem or config");
+static int validate_problem(const chisao_problem *p, int idx) {
+    if (!p) return fail(CHISAO_E_INVAL, "null problem");
     if (p->family < CHISAO_GAUSS || p->family > CHISAO_BUKIN6)
         return fail(CHISAO_E_INVAL, "problem %d: unknown family %d", idx, p->family);
     const bool closed = p->family >= CHISAO_RASTRIGIN;
@@ -171,6 +172,13 @@ static int validate(const chisao_problem *p, const chisao_config *c, int idx) {
                     return fail(CHISAO_E_INVAL, "problem %d: precision matrix %d not symmetric", idx, k);
             }
     }
+    return CHISAO_OK;
+}
+
+static int validate(const chisao_problem *p, const chisao_config *c, int idx) {
+    if (!p || !c) return fail(CHISAO_E_INVAL, "null problem or config");
+    int rc = validate_problem(p, idx);
+    if (rc) return rc;
     if (c->N < 1 || c->N > (1 << 30)) return fail(CHISAO_E_INVAL, "problem %d: N must be in 1..2^30", idx);
     if (c->m < 1 || c->m > 32) return fail(CHISAO_E_INVAL, "problem %d: m must be in 1..32", idx);
     if (c->n_osc < 1) return fail(CHISAO_E_INVAL, "problem %d: n_osc must be >= 1", idx);
@@ -1018,6 +1026,39 @@ extern "C" int chisao_mode_widths(chisao_handle h, int problem, float *w_out, in
     return CHISAO_OK;
 }
 
+// The launches of an evaluation on caller memory: value and adjoint gradient
+// in one pass, or the value and the central-difference stencils.  `a` carries
+// the device descriptors; results go to f_dev / G_dev (either may be null).
+static hipError_t ext_eval_launches(EvalArgs a, int d, int DP, int family, const float *X_dev, int B, float *f_dev,
+                                    float *G_dev, int grad_mode, hipStream_t st) {
+    a.X = X_dev;
+    a.x_stride = d;
+    a.out_stride = d;
+    a.ext_n = B;
+    a.vc_kind = kVcOne;
+    const long Vfd = 2 * d;
+    hipError_t e;
+    if (grad_mode == CHISAO_GRAD_ADJOINT) {
+        a.F_out = f_dev;
+        a.G_out = G_dev;
+        a.max_tiles = (B + 31) / 32;
+        return launch_eval(a, DP, family, kDirect, false, G_dev != nullptr, st);
+    }
+    if (f_dev) {
+        a.F_out = f_dev;
+        a.G_out = nullptr;
+        a.max_tiles = (B + 31) / 32;
+        if ((e = launch_eval(a, DP, family, kDirect, false, false, st)) != hipSuccess) return e;
+    }
+    if (G_dev) {
+        a.F_out = nullptr;
+        a.G_out = G_dev;
+        a.max_tiles = Vfd <= 32 ? (B + (32 / Vfd) - 1) / (32 / Vfd) : (long)B * ((Vfd + 31) / 32);
+        if ((e = launch_eval(a, DP, family, kDirect, true, false, st)) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 extern "C" int chisao_eval(chisao_handle h, int problem, const float *X_dev, int B, float *f_dev, float *G_dev,
                            int grad_mode) {
     if (!h) return fail(CHISAO_E_INVAL, "null handle");
@@ -1035,33 +1076,7 @@ extern "C" int chisao_eval(chisao_handle h, int problem, const float *X_dev, int
     c.grad_mode = grad_mode;
     c.pids = {problem};
     c.pids_dev = h->pid_seq + problem;
-    EvalArgs a = base_args(h, c);
-    a.X = X_dev;
-    a.x_stride = q.d;
-    a.out_stride = q.d;
-    a.ext_n = B;
-    a.vc_kind = kVcOne;
-    const long Vfd = 2 * q.d;
-    hipStream_t st = h->stream;
-    if (grad_mode == CHISAO_GRAD_ADJOINT) {
-        a.F_out = f_dev;
-        a.G_out = G_dev;
-        a.max_tiles = (B + 31) / 32;
-        HIP_TRY(launch_eval(a, q.DP, q.family, kDirect, false, G_dev != nullptr, st));
-        return CHISAO_OK;
-    }
-    if (f_dev) {
-        a.F_out = f_dev;
-        a.G_out = nullptr;
-        a.max_tiles = (B + 31) / 32;
-        HIP_TRY(launch_eval(a, q.DP, q.family, kDirect, false, false, st));
-    }
-    if (G_dev) {
-        a.F_out = nullptr;
-        a.G_out = G_dev;
-        a.max_tiles = Vfd <= 32 ? (B + (32 / Vfd) - 1) / (32 / Vfd) : (long)B * ((Vfd + 31) / 32);
-        HIP_TRY(launch_eval(a, q.DP, q.family, kDirect, true, false, st));
-    }
+    HIP_TRY(ext_eval_launches(base_args(h, c), q.d, q.DP, q.family, X_dev, B, f_dev, G_dev, grad_mode, h->stream));
     return CHISAO_OK;
 }
 
@@ -1113,5 +1128,140 @@ extern "C" int chisao_profile(chisao_handle h, int enable, chisao_kernel_profile
         memcpy(out, res, sizeof res);
     }
     h->ev_used.clear();
+    return CHISAO_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Evaluation without device allocation
+//
+// chisao_eval reads tables that chisao_init allocated: the fragment layouts of
+// the precision matrices, the centres, the log normalisers and the problem
+// descriptor.  chisao_eval_static builds the same tables for a problem given
+// directly, in a fixed device array instead, and runs the same kernels.  The
+// array is process-wide: each GPU holds one copy from library load to process
+// exit, and every call on that GPU overwrites it.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr size_t kScratchBytes = (size_t)8 << 20;
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_dev[kMaxDevices];  // device address of each GPU's copy, once looked up
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+// The device address of the current GPU's copy of `scratch`.  In host code the
+// array's name is only a stand-in; the runtime gives each device's address,
+// looked up once per device with that device current.
+static int scratch_base(unsigned char **out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(CHISAO_E_DEVICE, "device index %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(CHISAO_E_DEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_scratch_dev[dev] = (unsigned char *)ptr;
+    }
+    *out = g_scratch_dev[dev];
+    return CHISAO_OK;
+}
+
+extern "C" int chisao_eval_static(const chisao_problem *p, float fd_h, const float *X_dev, int B, float *f_dev,
+                                  float *G_dev, int grad_mode, void *hip_stream) {
+    int rc = validate_problem(p, 0);
+    if (rc) return rc;
+    if (B < 0) return fail(CHISAO_E_INVAL, "negative batch");
+    if (grad_mode != CHISAO_GRAD_FD && grad_mode != CHISAO_GRAD_ADJOINT) return fail(CHISAO_E_INVAL, "bad grad_mode");
+    if (!isfinite(fd_h)) return fail(CHISAO_E_INVAL, "non-finite fd_h");
+    const bool closed = p->family >= CHISAO_RASTRIGIN;
+    const size_t d = p->d, K = closed ? 0 : p->K, DP = pad_dim(p->d);
+    // scratch layout: descriptors, then the tables, each section 256-byte aligned
+    size_t used = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = used;
+        used = (used + bytes + 255) & ~(size_t)255;
+        return at;
+    };
+    const size_t o_pd = take(sizeof(ProblemDesc)), o_cls = take(sizeof(int)), o_ctl = take(sizeof(Ctl));
+    const size_t o_bad = take(sizeof(int)), o_lo = take(4 * d), o_hi = take(4 * d);
+    size_t o_pf = 0, o_mub = 0, o_lc = 0, o_w = 0, o_mu = 0, o_prec = 0;
+    if (!closed) {
+        o_pf = take(4 * K * DP * DP);
+        o_mub = take(4 * K * DP);
+        o_lc = take(4 * K);
+        o_w = take(4 * K);
+        o_mu = take(4 * K * d);
+        o_prec = take(4 * K * d * d);
+    }
+    if (used > kScratchBytes)
+        return fail(CHISAO_E_RANGE,
+                    "problem tables need %zu bytes, more than the %zu-byte static scratch (K = %zu at d = %zu)", used,
+                    kScratchBytes, K, d);
+    if (B == 0) return CHISAO_OK;
+    if (!X_dev) return fail(CHISAO_E_INVAL, "null X");
+    unsigned char *base = nullptr;
+    if ((rc = scratch_base(&base))) return rc;
+    hipStream_t st = (hipStream_t)hip_stream;
+    const float nu = p->family == CHISAO_STUDENT_T ? p->nu : 1.0f;
+    ProblemDesc q;
+    memset(&q, 0, sizeof q);
+    q.d = p->d;
+    q.DP = (int)DP;
+    q.K = (int)K;
+    q.family = p->family;
+    q.nu = nu;
+    q.nu_plus_d = nu + (float)p->d;
+    q.Pfrag = closed ? nullptr : (const float *)(base + o_pf);
+    q.muB = closed ? nullptr : (const float *)(base + o_mub);
+    q.logc2 = closed ? nullptr : (const float *)(base + o_lc);
+    q.lo = (const float *)(base + o_lo);
+    q.hi = (const float *)(base + o_hi);
+    q.N = B;
+    q.fd_h = fd_h;
+    q.noise_sigma = p->noise_sigma;  // recorded only: evaluations on caller memory carry no noise
+    Ctl ctl;
+    memset(&ctl, 0, sizeof ctl);
+    const int zero = 0;
+    // every section that must start at zero is written from the host: a fill
+    // of the same bytes would also do, this keeps the call to copies only
+    HIP_TRY(hipMemcpyAsync(base + o_pd, &q, sizeof q, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(base + o_cls, &zero, sizeof zero, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(base + o_ctl, &ctl, sizeof ctl, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(base + o_bad, &zero, sizeof zero, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(base + o_lo, p->lo, 4 * d, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(base + o_hi, p->hi, 4 * d, hipMemcpyHostToDevice, st));
+    if (!closed) {
+        HIP_TRY(hipMemcpyAsync(base + o_w, p->log_w, 4 * K, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(base + o_mu, p->mu, 4 * K * d, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(base + o_prec, p->prec, 4 * K * d * d, hipMemcpyHostToDevice, st));
+        HIP_TRY(launch_prepare(p->family, p->d, (int)DP, p->K, nu, (const float *)(base + o_w),
+                               (const float *)(base + o_mu), (const float *)(base + o_prec), (float *)(base + o_lc),
+                               (float *)(base + o_pf), (float *)(base + o_mub), (int *)(base + o_bad), st));
+    }
+    // one synchronization: the host descriptors above stay alive until their
+    // copies are done, and a matrix that is not positive definite is reported
+    // before anything is evaluated
+    int bad = 0;
+    HIP_TRY(hipMemcpyAsync(&bad, base + o_bad, sizeof bad, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (bad) return fail(CHISAO_E_INVAL, "a precision matrix is not positive definite");
+    EvalArgs a;
+    memset(&a, 0, sizeof a);
+    a.D.P = 1;
+    a.D.NT = B;
+    a.D.DS = (int)d;
+    a.D.mmax = 1;
+    a.D.Mmax = 1;
+    a.D.pd = (const ProblemDesc *)(base + o_pd);
+    a.D.ctl = (Ctl *)(base + o_ctl);
+    a.cls = (const int *)(base + o_cls);
+    a.n_cls = 1;
+    a.list_id = -1;
+    a.trial_next = -1;
+    a.nz_kind = -1;
+    HIP_TRY(ext_eval_launches(a, p->d, (int)DP, p->family, X_dev, B, f_dev, G_dev, grad_mode, st));
     return CHISAO_OK;
 }
