@@ -74,6 +74,33 @@ def _report(prob, X, F, Xall, Fall):
     return "\n".join(lines)
 
 
+def _copies_pass_fp64_stick_test(prob, cfg, X, Xall, tol):
+    """Second copies of a maximum: each must pass the stick test in FP64 at
+    its own position (the oracle's central-difference gradient, same step
+    rule and eps_grad, and the gate against the best recovered value), so the
+    FP64 method keeps it too once a sample stops there: deduplication removes
+    only points within eps_dup, and these lie farther apart.  Returns the
+    number of copies checked."""
+    from oracle import oracle as O
+
+    op = O.OracleProblem(prob)
+    owner = np.array([int(np.argmin(np.abs(Xall - x).max(1))) for x in X])
+    near = np.array([np.abs(Xall[j] - x).max() < tol[j] for j, x in zip(owner, X)])
+    n = 0
+    for j in set(owner[near].tolist()):
+        idx = np.nonzero(near & (owner == j))[0]
+        if len(idx) < 2:
+            continue
+        G = op.fd_grad(X[idx], cfg.fd_h) if cfg.grad_mode == 0 else op.eval(X[idx])[1]
+        f = op.eval(X[idx], grad=False)
+        print(f"  maximum {j}: {len(idx)} copies, FP64 |grad|_inf {np.abs(G).max(1)}, L-inf apart "
+              f"{np.abs(X[idx[0]] - X[idx[1:]]).max(1)}")
+        assert np.all(np.abs(G).max(1) < cfg.eps_grad)
+        assert np.all(f >= op.eval(X, grad=False).max() + cfg.log_delta)
+        n += len(idx) - 1
+    return n
+
+
 def _run_and_score(prob, cfg, x0, name):
     from oracle.modes import newton_modes
     from paper_2606_26164_amd.api import Optimizer
@@ -102,18 +129,21 @@ def _run_and_score(prob, cfg, x0, name):
           f"the gate of the best recovered value, recall {band_recall:.3f}; first cycle with the significant count "
           f"stuck: {first_full}; match tolerance up to {tol_all.max():.2e}")
     print(_report(prob, X, ms.F, Xall, Fall))
+    checked = _copies_pass_fp64_stick_test(prob, cfg, X, Xall, tol_all) if copies else 0
+    assert checked == copies
     return recall, not_a_max, band_recall, copies
 
 
 def test_gauss32_d16_recovers_the_significant_set():
     """d=16, K=32, N=16384, 200 cycles, central differences: all significant
-    modes; every recovered point is a maximum.  With FP32 central differences
-    the stick-test band reaches 4e-3 here, four times eps_dup, so a maximum
-    may come back twice (counted and limited, not forbidden)."""
+    modes; every recovered point is a maximum.  The stick test localises a
+    maximum only to |H^-1| eps_grad (up to 4e-3 here, four times eps_dup), so
+    two samples can stop at one maximum farther apart than eps_dup; every
+    such second copy is checked to pass the FP64 stick test and gate at its
+    position, i.e. the FP64 rule keeps it as well."""
     prob, cfg, x0 = W.gauss32_d16()
     recall, not_a_max, band_recall, copies = _run_and_score(prob, cfg, x0, "gauss32_d16 (d=16, K=32, N=16384, FD)")
     assert not_a_max == 0
-    assert copies <= 2
     assert band_recall == 1.0
     assert recall == 1.0
 
@@ -218,7 +248,10 @@ def test_batch64_batch_stuck_points_are_stationary_and_gated():
         hit += int(round(r * keep.sum()))
     print(f"\nbatch64: {len(items)} problems in {dt:.1f} s; {n_pts} points recovered: {n_max} distinct maxima, "
           f"{n_saddle} saddles, {n_dup} further copies of a maximum; significant modes recovered {hit}/{sig}")
-    assert n_max >= 0.9 * n_pts
+    # measured: 1139 of 1142 significant modes; 1139 maxima, 17 saddles and 7
+    # copies among 1163 points
+    assert hit >= 1135 and sig >= 1100
+    assert n_max >= 0.97 * n_pts and n_saddle + n_dup <= 35
 
 
 def test_student48_d32_noisy_student_t_full_run():
@@ -249,6 +282,17 @@ def test_student48_d32_noisy_student_t_full_run():
           f"{keep.sum()}, recall {recall:.3f}; points that are no distinct maximum {not_a_max}; "
           f"peak error max {max(err) if err else 0:.2e}; f_max {stats[-1]['f_max']:.3f}")
     print(_report(prob, X, ms.F, Xall, Fall))
-    assert len(X) >= 1
-    if len(ms.F):
-        assert ms.F.min() >= stats[-1]["f_max"] + cfg.log_delta - 1e-5
+    # Each recovered point is a distinct local maximum of the noise-free f.
+    # The gate compares gate values (noise s.d. sigma_n / sqrt(R)) with
+    # f_max + log delta, and f_max is the largest gate value over all stuck
+    # copies, so it sits a few s.d. above the highest peak and maxima within
+    # that margin of the significance threshold may miss the gate; every
+    # maximum more than 3 s.d. above the run's own threshold is recovered.
+    assert not_a_max == 0
+    assert max(err) <= 1e-3
+    assert ms.F.min() >= stats[-1]["f_max"] + cfg.log_delta - 1e-5
+    sd = prob.noise_sigma / np.sqrt(cfg.gate_reps)
+    clear = Fall >= stats[-1]["f_max"] + cfg.log_delta + 3 * sd
+    clear_recall, _ = _score(X, Xall[clear], tol_all[clear])
+    print(f"maxima clear of the gate: {int(clear.sum())}, recovered {clear_recall:.3f}")
+    assert clear.sum() >= 4 and clear_recall == 1.0
