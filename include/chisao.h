@@ -26,6 +26,7 @@
 #ifndef CHISAO_H
 #define CHISAO_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -326,6 +327,24 @@ typedef struct {
 /* Writes one entry per class (at most cap) and the class count to *n_out;
  * cap too small: CHISAO_E_RANGE with *n_out set.  Host memory. */
 int chisao_tuning(chisao_handle h, chisao_tuning_entry *out, int cap, int *n_out);
+
+/* Measured ceilings of the GPU the call runs on, against which kernel
+ * throughput is priced beside the published figures (FP32 matrix 157.3
+ * TFLOP/s, HBM 8 TB/s on MI355X).  fp32_mfma_tflops: a full grid of waves each
+ * issuing a long run of v_mfma_f32_16x16x4f32 on independent accumulators;
+ * hbm_copy_gbs: a streaming copy between two device buffers of copy_bytes each
+ * (read + write bytes over time; 1 MiB .. 32 GiB, a few GiB keeps the caches
+ * out of it).  Best of several timed repetitions with HIP events on
+ * hip_stream.  Allocates and frees the two copy buffers; synchronizes. */
+typedef struct {
+    double fp32_mfma_tflops;
+    double mfma_flops;  /* flops of one timed matrix launch */
+    double mfma_ms;
+    double hbm_copy_gbs;
+    double copy_bytes;  /* bytes read plus bytes written by one timed copy */
+    double copy_ms;
+} chisao_peaks;
+int chisao_measure_peaks(chisao_peaks *out, size_t copy_bytes, void *hip_stream);
 
 #ifdef __cplusplus
 }

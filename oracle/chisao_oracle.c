@@ -1444,3 +1444,16 @@ int orc_num_threads(void)
     return 1;
 #endif
 }
+
+/* Thread count of the parallel per-sample loops (results do not depend on
+ * it); n < 1 leaves it unchanged.  Returns the count now in effect. */
+int orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}

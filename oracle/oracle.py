@@ -103,6 +103,8 @@ def _bind(L):
     L.orc_phase_anti.argtypes = [P(_Problem), C.c_void_p, P(_Config), P(_State)]
     L.orc_init_population.argtypes = [P(_Problem), P(_Config), C.c_void_p]
     L.orc_num_threads.restype = C.c_int
+    L.orc_set_num_threads.argtypes = [C.c_int]
+    L.orc_set_num_threads.restype = C.c_int
     return L
 
 
@@ -142,6 +144,11 @@ def philox4x32_10(ctr, key):
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n: int) -> int:
+    """Thread count of the oracle's per-sample loops (results do not depend on it)."""
+    return int(lib().orc_set_num_threads(int(n)))
 
 
 class OracleProblem:

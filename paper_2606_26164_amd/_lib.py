@@ -56,6 +56,11 @@ class TuningEntry(C.Structure):
                 ("ms", C.c_float * 4)]
 
 
+class Peaks(C.Structure):
+    _fields_ = [("fp32_mfma_tflops", C.c_double), ("mfma_flops", C.c_double), ("mfma_ms", C.c_double),
+                ("hbm_copy_gbs", C.c_double), ("copy_bytes", C.c_double), ("copy_ms", C.c_double)]
+
+
 class KernelProfile(C.Structure):
     _fields_ = [("launches", C.c_int32), ("ms", C.c_double), ("points", C.c_int64)]
 
@@ -65,7 +70,8 @@ PROF_NAMES = ("eval_direct", "eval_trial", "eval_probe", "eval_fd", "lbfgs", "lb
 
 EXPORTS = ("chisao_init", "chisao_init_batched", "chisao_profile", "chisao_cycle", "chisao_modes",
            "chisao_mode_widths", "chisao_get_state", "chisao_set_state", "chisao_run_phases", "chisao_eval",
-           "chisao_destroy", "chisao_last_error", "chisao_tuning", "chisao_eval_static")
+           "chisao_destroy", "chisao_last_error", "chisao_tuning", "chisao_eval_static",
+           "chisao_measure_peaks")
 
 _lib = None
 
@@ -100,6 +106,8 @@ def load(path: str = LIB_PATH):
     L.chisao_eval_static.argtypes = [P(Problem), C.c_float, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int,
                                      C.c_void_p]
     L.chisao_eval_static.restype = C.c_int
+    L.chisao_measure_peaks.argtypes = [P(Peaks), C.c_size_t, C.c_void_p]
+    L.chisao_measure_peaks.restype = C.c_int
     L.chisao_profile.argtypes = [C.c_void_p, C.c_int, P(KernelProfile)]
     L.chisao_profile.restype = C.c_int
     L.chisao_destroy.argtypes = [C.c_void_p]

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libchisao.so")
-SOURCES = ["eval.hip", "cycle.hip", "api.hip"]
+SOURCES = ["eval.hip", "cycle.hip", "api.hip", "peaks.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed-FP32 VALU instructions are kept out of the generated code: the
