@@ -109,6 +109,23 @@ __device__ __forceinline__ float rows4_sum(float v) {
     return __uint_as_float(b[0]) + __uint_as_float(b[1]);
 }
 
+// Two values per lane summed over the four rows at once: on return rows 0
+// and 2 hold the row sum of a, rows 1 and 3 that of b, each added in the
+// order of rows4_sum ((r0 + r1) + (r2 + r3)), so bitwise the same.
+__device__ __forceinline__ float rows4_sum_pair(float a, float b) {
+    const auto s = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    const float h = __uint_as_float(s[0]) + __uint_as_float(s[1]);
+    const auto t = __builtin_amdgcn_permlane32_swap(__float_as_uint(h), __float_as_uint(h), false, false);
+    return __uint_as_float(t[0]) + __uint_as_float(t[1]);
+}
+// The inverse split: x holds a value of block 0 in rows 0 and 2 and one of
+// block 1 in rows 1 and 3; every lane receives both.
+__device__ __forceinline__ void rows_pair_split(float x, float &b0, float &b1) {
+    const auto s = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+    b0 = __uint_as_float(s[0]);
+    b1 = __uint_as_float(s[1]);
+}
+
 // Total order on floats as signed ints, for exact atomic max.
 __device__ __forceinline__ int float_to_ordered(float f) {
     int i = __float_as_int(f);

@@ -65,6 +65,31 @@ __device__ __forceinline__ void load_frag(const gfloat *p, float out[MB]) {
     }
 }
 
+// Raw buffer resource over a read-only table of `bytes` bytes (gfx9
+// descriptor; loads past the end return zero).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t table_rsrc(const float *base, uint32_t bytes) {
+    // the table pointer is the same in every lane; passing it through
+    // readfirstlane puts the resource in scalar registers
+    const uint64_t a = reinterpret_cast<uint64_t>(base);
+    const uint64_t u = (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)a) |
+                       ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(a >> 32)) << 32);
+    return __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<float *>(u), (short)0,
+                                             __builtin_amdgcn_readfirstlane((int)bytes), 0x00020000);
+}
+
+template <int MB>
+__device__ __forceinline__ void load_frag_buf(__amdgpu_buffer_rsrc_t rs, int voff, int soff, float out[MB]) {
+    if constexpr (MB == 4) {
+        const f32x4 v = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, voff, soff, 0));
+        out[0] = v[0]; out[1] = v[1]; out[2] = v[2]; out[3] = v[3];
+    } else if constexpr (MB == 2) {
+        const f32x2 v = __builtin_bit_cast(f32x2, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 0));
+        out[0] = v[0]; out[1] = v[1];
+    } else {
+        out[0] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, voff, soff, 0));
+    }
+}
+
 // One component's operands in registers: precision-matrix fragments,
 // centre coordinates in B-operand lane order, log2 weight.
 template <int KS, int MB>
@@ -367,7 +392,10 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
             if (pref[mid] <= tile) lo_j = mid;
             else hi_j = mid - 1;
         }
-        const int p = a.cls[lo_j];
+        // every lane finds the same problem; saying so keeps its descriptor,
+        // table pointers and the component loop's addressing in scalar
+        // registers instead of per-lane 64-bit arithmetic
+        const int p = __builtin_amdgcn_readfirstlane(a.cls[lo_j]);
         const ProblemDesc &pd = D.pd[p];
         const int ltile = tile - pref[lo_j];
         const int d = pd.d;
@@ -547,25 +575,41 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
             // works through the log-sum-exp epilogue on the VALU, the other keeps
             // the matrix core busy; a wave raises its priority for the duration of
             // its MFMA block so the arbiter keeps the matrix core fed.  Operands
-            // come through global-address-space pointers: flat loads would also
-            // count against the LDS counter, and the cross-lane reductions of the
-            // epilogue would then wait for them.
-            const gfloat *Pfrag = as_global(pd.Pfrag), *muBk = as_global(pd.muB), *logc2 = as_global(pd.logc2);
+            // come through buffer loads, which only the vector-memory counter
+            // tracks: flat loads would also count against the LDS counter, and
+            // the cross-lane reductions of the epilogue would then wait for them.
             const float nu = pd.nu, nupd = pd.nu_plus_d;
             CompRegs<KS, MB> ra;
+            // Buffer loads: a scalar resource per table and the component's
+            // byte offset in a scalar register, each lane's fixed offset in a
+            // vector register, so the loop advances one scalar per table
+            // instead of per-lane 64-bit addresses.
+            const int Kc = pd.K;
+            const __amdgpu_buffer_rsrc_t rs_pf = table_rsrc(pd.Pfrag, (uint32_t)Kc * DP * DP * 4u);
+            const __amdgpu_buffer_rsrc_t rs_mu = table_rsrc(pd.muB, (uint32_t)Kc * DP * 4u);
+            const __amdgpu_buffer_rsrc_t rs_lc = table_rsrc(pd.logc2, (uint32_t)Kc * 4u);
+            const int pf_lane = lane * MB * 4, mu_lane = g * KS * 4;
             auto load = [&](int k, CompRegs<KS, MB> &r) {
-                const gfloat *pf = Pfrag + (size_t)k * KS * kWave * MB + lane * MB;
-                const gfloat *mb_p = muBk + ((size_t)k * 4 + g) * KS;
+                const int pf_k = k * DP * DP * 4, mu_k = k * DP * 4;
 #pragma unroll
-                for (int ks = 0; ks < KS; ++ks) load_frag<MB>(pf + (size_t)ks * kWave * MB, r.pa[ks]);
+                for (int ks = 0; ks < KS; ++ks) load_frag_buf<MB>(rs_pf, pf_lane + ks * kWave * MB * 4, pf_k, r.pa[ks]);
 #pragma unroll
                 for (int i = 0; i < KS; i += 4) {
-                    const f32x4 vb = *reinterpret_cast<const gf32x4 *>(mb_p + i);
+                    const f32x4 vb = __builtin_bit_cast(
+                        f32x4, __builtin_amdgcn_raw_buffer_load_b128(rs_mu, mu_lane + i * 4, mu_k, 0));
                     r.muB[i] = vb[0]; r.muB[i + 1] = vb[1]; r.muB[i + 2] = vb[2]; r.muB[i + 3] = vb[3];
                 }
-                r.lc2 = logc2[k];
+                r.lc2 = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs_lc, 0, k * 4, 0));
             };
             // contracts one component for the first NBA column blocks of the tile
+            // log-sum-exp state of the lane's own block in the two-block path
+            float m_own = -INFINITY, s_own = 0.0f;
+            auto own_to_blocks = [&](auto nba) {
+                if constexpr (decltype(nba)::value == 2) {
+                    rows_pair_split(m_own, mrun[0], mrun[1]);
+                    rows_pair_split(s_own, srun[0], srun[1]);
+                }
+            };
             auto step = [&](const CompRegs<KS, MB> &r, auto nba) {
                 constexpr int NBA = decltype(nba)::value;
                 f32x4 acc[NB][MB];
@@ -591,6 +635,57 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
                     }
                 }
                 __builtin_amdgcn_s_setprio(0);
+                if constexpr (NBA == 2) {
+                    // Both blocks' quadratic forms reduced in one exchange;
+                    // rows 0 and 2 then carry block 0's log-sum-exp state and
+                    // rows 1 and 3 block 1's (the same arithmetic as the
+                    // per-block path below, half the lanes' work each), and
+                    // the gradient weights are exchanged back to every lane.
+                    float q0 = 0.0f, q1 = 0.0f;
+#pragma unroll
+                    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                        for (int rr = 0; rr < 4; ++rr) {
+                            q0 = fmaf(bv[0][4 * mb + rr], acc[0][mb][rr], q0);
+                            q1 = fmaf(bv[1][4 * mb + rr], acc[1][mb][rr], q1);
+                        }
+                    const float q = rows4_sum_pair(q0, q1);
+                    float l2, w = 1.0f;
+                    if constexpr (FAM == 0) {
+                        l2 = r.lc2 - q * (0.5f * kLog2e);
+                    } else {
+                        l2 = r.lc2 - (0.5f * nupd * kLog2e) * log1pf(q / nu);
+                        w = nupd / (nu + q);
+                    }
+                    const bool moved = l2 > m_own + kLseSlack;
+                    const float mnew = moved ? l2 : m_own;
+                    const float sc = __builtin_amdgcn_exp2f(m_own - mnew);
+                    const float pk = __builtin_amdgcn_exp2f(l2 - mnew);
+                    s_own = fmaf(s_own, sc, pk);
+                    m_own = mnew;
+                    if constexpr (GRAD) {
+                        if (__any(moved)) {
+                            // sc is exactly 1 in the block that did not move
+                            float sc0, sc1;
+                            rows_pair_split(sc, sc0, sc1);
+#pragma unroll
+                            for (int i = 0; i < KS; ++i) {
+                                gacc[0][i] *= sc0;
+                                gacc[1][i] *= sc1;
+                            }
+                        }
+                        float pw0, pw1;
+                        rows_pair_split(pk * w, pw0, pw1);
+#pragma unroll
+                        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                            for (int rr = 0; rr < 4; ++rr) {
+                                gacc[0][mb * 4 + rr] = fmaf(pw0, acc[0][mb][rr], gacc[0][mb * 4 + rr]);
+                                gacc[1][mb * 4 + rr] = fmaf(pw1, acc[1][mb][rr], gacc[1][mb * 4 + rr]);
+                            }
+                    }
+                    return;
+                }
 #pragma unroll
                 for (int nb = 0; nb < NBA; ++nb) {
                     float q = 0.0f;
@@ -630,7 +725,8 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
                 }
             };
             const int K = pd.K;
-            const int kb = SPLIT == 1 ? 0 : (wv * K) / SPLIT, ke = SPLIT == 1 ? K : ((wv + 1) * K) / SPLIT;
+            const int wvu = __builtin_amdgcn_readfirstlane(wv);
+            const int kb = SPLIT == 1 ? 0 : (wvu * K) / SPLIT, ke = SPLIT == 1 ? K : ((wvu + 1) * K) / SPLIT;
             if constexpr (DP < 64) {
                 // small components: too little work per component to hide its load
                 // latency behind the other wave, so the next one is loaded into a
@@ -649,6 +745,7 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
                             step(rb, nba);
                         }
                     }
+                    own_to_blocks(nba);
                 };
                 if constexpr (HALF) {
                     if (ppw < PPW) run(OneBlock{});
@@ -662,6 +759,7 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
                         load(k, ra);
                         step(ra, nba);
                     }
+                    own_to_blocks(nba);
                 };
                 if constexpr (HALF) {
                     if (ppw < PPW) run(OneBlock{});
