@@ -140,7 +140,8 @@ typedef struct {
 /* Per-cycle statistics (host struct). */
 typedef struct {
     int32_t k;          /* 1-based index of the cycle these figures belong to */
-    float f_max;        /* largest value over active samples after Phase 1 (gate values when noisy) */
+    float f_max;        /* largest value over active samples after Phase 1; with noise, the sample with the largest
+                           gate value is re-estimated with gate_reps fresh draws and that estimate is f_max */
     int32_t n_stuck;    /* samples passing the stick test (before deduplication) */
     int32_t K_lost;     /* duplicates removed by Phase 3 */
     int32_t n_modes;    /* stuck samples surviving deduplication */

@@ -818,7 +818,8 @@ int orc_lbfgs_iterate(const orc_problem *P, const double *logc, const orc_config
 }
 
 /* ------------------------------------------------------------------------ */
-/* Phase 2: stick test.  f_max is the largest value over active samples;     */
+/* Phase 2: stick test.  f_max is the largest value over active samples     */
+/* (with noise: re-estimated at the sample with the largest gate value);     */
 /* stuck = (|grad f|_inf < eps_grad) and (f >= f_max + log delta).           */
 /* ------------------------------------------------------------------------ */
 /* The value the quality gate, the deduplication order and the mode output
@@ -864,6 +865,7 @@ static int compute_gate_values(const orc_problem *P, const double *logc, const o
 int orc_phase_stick(const orc_problem *P, const double *logc, const orc_config *C, orc_state *S, orc_replay *R)
 {
     int N = C->N, d = P->d;
+    if (N < 1) return ORC_EINVAL;
     if (P->noise_sigma > 0.0) {
         if (!S->Fg) return ORC_EINVAL;
         int rc = compute_gate_values(P, logc, C, S);
@@ -885,8 +887,32 @@ int orc_phase_stick(const orc_problem *P, const double *logc, const orc_config *
     }
     S->n_nonfinite = nbad;
     double fmax_ = -INFINITY;
+    int best = -1;
     for (int i = 0; i < N; ++i)
-        if (S->active[i] && Fv[i] > fmax_) fmax_ = Fv[i];
+        if (S->active[i] && Fv[i] > fmax_) {
+            fmax_ = Fv[i];
+            best = i;
+        }
+    if (P->noise_sigma > 0.0 && best >= 0) {
+        /* Reading (noise): the largest gate value over many samples, most of
+         * them copies of the same peak, overestimates that peak by the
+         * largest of their noise terms.  f_max is instead the objective at
+         * the sample with the largest gate value, estimated afresh: f there
+         * plus sigma_n times the mean of R new normals (GATE stream,
+         * sub-stream 1), unbiased for f at that sample. */
+        int R = C->gate_reps > 0 ? C->gate_reps : C->M;
+        double zs = 0.0;
+        for (int b = 0; 4 * b < R; ++b) {
+            double z[4];
+            normals4(C, (uint32_t)best, (uint32_t)S->k + 1u, ((uint32_t)PH_GATE << 24) | 1u, (uint32_t)b, z);
+            for (int q = 0; q < 4 && 4 * b + q < R; ++q) zs += z[q];
+        }
+        double *work = (double *)malloc(sizeof(double) * eval_work_len(P));
+        if (!work) return ORC_ENOMEM;
+        double f_best = eval_point(P, logc, S->X + (size_t)best * d, NULL, work);
+        free(work);
+        fmax_ = f_best + P->noise_sigma * (zs / R);
+    }
     S->f_max = fmax_;
     double gate = fmax_ + C->log_delta;
     sample_replay_t *sr = (sample_replay_t *)calloc((size_t)N, sizeof(sample_replay_t));

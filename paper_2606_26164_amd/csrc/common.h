@@ -178,6 +178,7 @@ struct Ctl {
     int k;  // cycles completed
     int count[kNumLists];
     int fmax_ord;  // ordered-int image of f_max
+    unsigned long long fmax_key;  // largest (value, -index) over the gate values: finds the best sample
     int n_stuck, K_lost, n_modes, n_active;
     int reseed_kind;  // 0 none, 1 RM, 2 GR, 3 deactivate
     int gr_disabled, gr_fail, gr_used_last, gr_prev_modes;

@@ -479,6 +479,7 @@ __global__ void stick_reset_kernel(Dev D) {
     D.ctl[p].count[L_STK] = 0;
     D.ctl[p].n_stuck = 0;
     D.ctl[p].fmax_ord = float_to_ordered(-INFINITY);
+    D.ctl[p].fmax_key = 0ull;
 }
 
 // A sample whose value, gate value or gradient is not finite leaves the
@@ -490,28 +491,67 @@ __device__ __forceinline__ bool sample_finite(const Dev &D, const ProblemDesc &p
     return ok;
 }
 
+// (value, lower index first) as one unsigned key: the largest key is the
+// sample with the largest value, the lowest index among equal ones
+__device__ __forceinline__ unsigned long long value_index_key(float v, int i) {
+    const uint32_t ord = (uint32_t)float_to_ordered(v) ^ 0x80000000u;
+    return ((unsigned long long)ord << 32) | (unsigned long long)(0xFFFFFFFFu - (uint32_t)i);
+}
+
 __global__ void fmax_kernel(Dev D) {
-    __shared__ float red[kBlock];
+    __shared__ unsigned long long red[kBlock];
     const int p = blockIdx.y;
     const ProblemDesc &pd = D.pd[p];
-    float v = -INFINITY;
+    unsigned long long key = 0ull;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < pd.N; i += gridDim.x * blockDim.x) {
         const int s = pd.s0 + i;
         if (!D.active[s]) continue;
         if (sample_finite(D, pd, s)) {
-            v = fmaxf(v, gate_values(D, pd)[s]);
+            const unsigned long long k = value_index_key(gate_values(D, pd)[s], i);
+            key = k > key ? k : key;
         } else {
             D.active[s] = 0;
             atomicAdd(&D.ctl[p].n_nonfinite, 1);
         }
     }
-    red[threadIdx.x] = v;
+    red[threadIdx.x] = key;
     __syncthreads();
     for (int o = kBlock / 2; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + o]);
+        if ((int)threadIdx.x < o && red[threadIdx.x + o] > red[threadIdx.x]) red[threadIdx.x] = red[threadIdx.x + o];
         __syncthreads();
     }
-    if (threadIdx.x == 0) atomicMax(&D.ctl[p].fmax_ord, float_to_ordered(red[0]));
+    if (threadIdx.x == 0 && red[0]) {
+        atomicMax(&D.ctl[p].fmax_key, red[0]);
+        atomicMax(&D.ctl[p].fmax_ord, float_to_ordered(gate_values(D, pd)[pd.s0 + (int)(0xFFFFFFFFu - (uint32_t)red[0])]));
+    }
+}
+
+// Noisy problems: the largest gate value over many copies of one peak
+// overestimates it by the largest of their noise terms, so f_max is the
+// gate value of the best sample with its noise replaced by the mean of
+// gate_reps new draws (GATE stream, sub-stream 1): an unbiased estimate of f
+// there.  One thread per problem.
+__global__ void fmax_redraw_kernel(Dev D) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= D.P) return;
+    const ProblemDesc &pd = D.pd[p];
+    const unsigned long long key = D.ctl[p].fmax_key;
+    if (!(pd.noise_sigma > 0.0f) || key == 0ull) return;
+    const int i = (int)(0xFFFFFFFFu - (uint32_t)key);
+    const uint32_t kcyc = (uint32_t)D.ctl[p].k + 1u;
+    float zs_old = 0.0f, zs_new = 0.0f;
+    for (int b = 0; 4 * b < pd.gate_reps; ++b) {
+        float zo[4], zn[4];
+        box_muller4(philox((uint32_t)i, kcyc, kGate << 24, (uint32_t)b, pd.key0, pd.key1), zo);
+        box_muller4(philox((uint32_t)i, kcyc, (kGate << 24) | 1u, (uint32_t)b, pd.key0, pd.key1), zn);
+        for (int q = 0; q < 4 && 4 * b + q < pd.gate_reps; ++q) {
+            zs_old += zo[q];
+            zs_new += zn[q];
+        }
+    }
+    const float R = (float)pd.gate_reps;
+    const float fmax = D.Fg[pd.s0 + i] + pd.noise_sigma * (zs_new / R - zs_old / R);
+    D.ctl[p].fmax_ord = float_to_ordered(fmax);
 }
 
 __global__ void stick_kernel(Dev D) {
@@ -534,6 +574,7 @@ hipError_t launch_stick(const Dev &D, hipStream_t st) {
     const dim3 grid(grid_for(D.NT / D.P + 1, kBlock, 256), D.P), block(kBlock);
     hipLaunchKernelGGL(stick_reset_kernel, dim3(grid_for(D.P, 64)), dim3(64), 0, st, D);
     hipLaunchKernelGGL(fmax_kernel, grid, block, 0, st, D);
+    hipLaunchKernelGGL(fmax_redraw_kernel, dim3(grid_for(D.P, 64)), dim3(64), 0, st, D);
     hipLaunchKernelGGL(stick_kernel, grid, block, 0, st, D);
     return hipGetLastError();
 }

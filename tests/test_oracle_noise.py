@@ -75,8 +75,40 @@ def test_gate_value_is_mean_of_R_noisy_evaluations():
         # the gate value and the line-search value are different draws
         zf = (run.F - f_clean) / SIGMA
         assert abs(np.corrcoef(z, zf)[0, 1]) < 5.0 / np.sqrt(len(z))
-        # f_max and the stick test use the gate values
-        assert run.stats()["f_max"] == run.Fg.max()
+        # the stick test compares gate values with f_max, which is estimated
+        # afresh at the sample with the largest gate value
+        best = int(np.argmax(np.where(run.active == 1, run.Fg, -np.inf)))
+        fm = run.stats()["f_max"]
+        assert fm != run.Fg.max() and abs(fm - f_clean[best]) < 6 * SIGMA / np.sqrt(R)
+        gate = fm + cfg.log_delta
+        np.testing.assert_array_equal(run.stuck, (np.abs(run.G).max(1) < cfg.eps_grad) & (run.Fg >= gate))
+
+
+def test_f_max_is_an_unbiased_fresh_estimate_at_the_best_gate_sample():
+    """With many samples near one peak, the largest gate value overestimates
+    the peak by the largest of their noise terms.  f_max is f at the sample
+    with the largest gate value plus sigma_n times the mean of R new draws:
+    over independent runs its residual is N(0, sigma_n^2 / R), unbiased, and
+    uncorrelated with that sample's gate noise, while the largest gate value's
+    residual is biased upward."""
+    prob = _noisy_problem()
+    R = 8
+    fresh, maxg, own = [], [], []
+    for seed in range(400):
+        cfg = W.RunConfig(N=256, n_conv=1, M=8, eps_grad=1e-3, seed=1000 + seed, gate_reps=R)
+        x0 = W.uniform_population(5, 256, prob.lo, prob.hi)
+        run = O.OracleRun(prob, cfg, x0)
+        run.cc.n_conv = 0
+        run.phase_converge()
+        run.phase_stick()
+        f_clean = O.OracleProblem(prob).eval(x0, grad=False)
+        best = int(np.argmax(run.Fg))
+        fresh.append((run.stats()["f_max"] - f_clean[best]) / SIGMA)
+        maxg.append((run.Fg[best] - f_clean[best]) / SIGMA)
+    fresh, maxg = np.array(fresh), np.array(maxg)
+    _assert_standard_normal(fresh, var=1.0 / R)
+    assert abs(np.corrcoef(fresh, maxg)[0, 1]) < 5.0 / np.sqrt(len(fresh))
+    assert maxg.mean() > 5.0 * np.sqrt(1.0 / R / len(maxg))
 
 
 def test_noise_free_problem_ignores_gate_reps():
