@@ -1,9 +1,10 @@
 // Measured machine peaks: the two ceilings the kernels are priced against.
 //
 // FP32 matrix throughput: every wave of a full grid issues a long run of
-// v_mfma_f32_16x16x4f32 on eight independent accumulators (more chains than
-// the instruction's issue latency needs), so the matrix cores never wait on a
-// dependency.  HBM bandwidth: a 16-byte-per-lane streaming copy between two
+// v_mfma_f32_16x16x4f32 on sixteen independent accumulators, so the matrix
+// cores never wait on a dependency (with eight, the compiler rotates
+// accumulator registers through moves and a wait state every iteration, and
+// the loop runs 9% slower).  HBM bandwidth: a streaming copy (four 16-byte loads per lane) between two
 // buffers far larger than the last-level caches.  Both are timed with HIP
 // events on the caller's stream and report the best of a few repetitions.
 #include <hip/hip_runtime.h>
@@ -16,8 +17,8 @@ namespace {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kChains = 8;
-constexpr int kMfmaIters = 4096;
+constexpr int kChains = 16;
+constexpr int kMfmaIters = 2048;
 constexpr int kMfmaBlocks = 256 * 8;  // 8 workgroups of four waves per CU
 constexpr int kMfmaThreads = 256;
 
@@ -38,10 +39,26 @@ __global__ __launch_bounds__(kMfmaThreads) void mfma_peak_kernel(float seed, flo
     if (s == 12345.678f) sink[blockIdx.x] = s;
 }
 
+// Four independent 16-byte loads in flight per lane, streamed past the
+// caches (nontemporal); the fastest of the copy variants timed on MI355X
+// (grids of 1k-32k workgroups, 1-8 loads per lane, with and without the
+// hint: 4.5-5.4 TB/s).
+constexpr int kCopyUnroll = 4;
+constexpr int kCopyBlocks = 256 * 128;
 __global__ __launch_bounds__(256) void copy_kernel(const f32x4 *__restrict__ src, f32x4 *__restrict__ dst, size_t n) {
     const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + (kCopyUnroll - 1) * stride < n; i += kCopyUnroll * stride) {
+        f32x4 v[kCopyUnroll];
+#pragma unroll
+        for (int u = 0; u < kCopyUnroll; ++u) v[u] = __builtin_nontemporal_load(src + i + u * stride);
+#pragma unroll
+        for (int u = 0; u < kCopyUnroll; ++u) __builtin_nontemporal_store(v[u], dst + i + u * stride);
+    }
+    for (; i < n; i += stride) dst[i] = src[i];
 }
+
+constexpr int kWarmLaunches = 40;
 
 template <class F>
 hipError_t best_ms(hipStream_t st, int reps, F &&launch, float *best) {
@@ -54,6 +71,10 @@ hipError_t best_ms(hipStream_t st, int reps, F &&launch, float *best) {
         return e;
     }
     *best = 0.0f;
+    // untimed launches first: from idle the clocks take tens of milliseconds
+    // to ramp up, and a short timed run would price the kernels against a
+    // cold chip
+    for (int r = 0; r < kWarmLaunches && e == hipSuccess; ++r) e = launch();
     for (int r = 0; r <= reps && e == hipSuccess; ++r) {  // repetition 0 warms up
         e = hipEventRecord(e0, st);
         if (e == hipSuccess) e = launch();
@@ -90,7 +111,7 @@ extern "C" int chisao_measure_peaks(chisao_peaks *out, size_t copy_bytes, void *
         }, &ms_mfma);
     if (e == hipSuccess)
         e = best_ms(st, 5, [&] {
-            hipLaunchKernelGGL(copy_kernel, dim3(256 * 64), dim3(256), 0, st, src, dst, n4);
+            hipLaunchKernelGGL(copy_kernel, dim3(kCopyBlocks), dim3(256), 0, st, src, dst, n4);
             return hipGetLastError();
         }, &ms_copy);
     if (sink) (void)hipFree(sink);
