@@ -11,9 +11,12 @@ The metric counts sample-iterations nominally: N * (n_conv + n_cloud + n_anti)
 per cycle, masked samples included; the active count (samples that actually
 took each step) is reported beside it.  `value` is the adjoint-gradient
 throughput; the finite-difference throughput on the same schedule and the
-ratio between the two are reported beside it, together with the roofline
-position of the dominant kernel (HIP events around its launches during the
-timed cycles, priced against the published and the measured peaks), the
+ratio between the two are reported beside it.  The timed cycles run as the
+library runs them by default, one captured hipGraph replayed per cycle; a few
+further cycles are then launched one by one with HIP events around every
+launch, which give the roofline position of the dominant kernel (priced
+against the published and the measured peaks), the kernel time breakdown and
+the active share of the sample-iterations.  Also reported: the
 other workloads' throughput (d=16 finite differences, the 64-problem batch,
 the noisy Student-t mixture, a closed form), the mode recall of a full run
 against the FP64 reference, and the FP64 CPU oracle's throughput on bounded
@@ -130,9 +133,12 @@ def measure_peaks(copy_gib: int = 4):
                      f"{copy_gib} GiB (read + write bytes over time); best of several repetitions")
 
 
-def run_gpu(items, warmup, steps, profile=True):
-    """Warm-up cycles, then `steps` timed cycles (with per-launch events when
-    profiling).  items: [(problem, config, x0)]; one handle for all of them."""
+def run_gpu(items, warmup, steps, profile_steps=0):
+    """Warm-up cycles, then `steps` timed cycles as the library runs them by
+    default (one captured hipGraph replayed per cycle), then `profile_steps`
+    further cycles launched one by one with HIP events around every launch
+    (kernel times, evaluation counts, cycle statistics).  items: [(problem,
+    config, x0)]; one handle for all of them."""
     import torch
 
     from paper_2606_26164_amd.api import Optimizer
@@ -146,37 +152,43 @@ def run_gpu(items, warmup, steps, profile=True):
         torch.cuda.synchronize()
         per_cycle.append(time.perf_counter() - t)
     torch.cuda.synchronize()
-    if profile:
-        opt.profile_begin()
     t0 = time.perf_counter()
-    stats = opt.cycle(steps, stats=True) if steps > 0 else []
+    if steps > 0:
+        opt.cycle(steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    prof = opt.profile_end() if profile else {}
+    stats, prof, tp = [], {}, 0.0
+    if profile_steps > 0:
+        opt.profile_begin()
+        t2 = time.perf_counter()
+        stats = opt.cycle(profile_steps, stats=True)
+        tp = time.perf_counter() - t2
+        prof = opt.profile_end()
     opt.close()
     if len(items) == 1:
         stats = [[s] for s in stats]
-    return dict(seconds=t1 - t0, warmup_seconds=per_cycle, stats=stats, profile=prof)
+    return dict(seconds=t1 - t0, warmup_seconds=per_cycle, stats=stats, profile=prof, profile_seconds=tp,
+                profile_steps=profile_steps)
 
 
 def nominal_si(items, last=False):
     return sum(c.N * (c.n_conv + (0 if last else c.n_cloud + c.n_anti)) for _, c, _ in items)
 
 
-def active_si(items, r):
-    """Sample-iterations of the timed cycles counting only the samples that
-    took each step: L-BFGS steppers (counted on the device) plus the unfrozen
-    samples of every smoothing and anti-convergence step."""
+def active_fraction(items, r):
+    """Share of the nominal sample-iterations of the profiled cycles that the
+    samples actually took: L-BFGS steppers (counted on the device) plus the
+    unfrozen samples of every smoothing and anti-convergence step."""
     lb = r["profile"].get("lbfgs", {}).get("points", 0)
     expl = 0
     for cyc in r["stats"]:
         for (_, c, _), s in zip(items, cyc):
             expl += s["n_unfrozen"] * (c.n_cloud + c.n_anti)
-    return lb + expl
+    return (lb + expl) / (nominal_si(items) * max(r["profile_steps"], 1))
 
 
 def eval_roofline(items, r, peaks, dominant_only=True):
-    """Roofline of the evaluation launches over the timed cycles.  With one
+    """Roofline of the evaluation launches over the profiled cycles.  With one
     problem the dominant launch kind (by time); otherwise all evaluation
     launches of the handle, with the problems' own evaluation counts."""
     prof = r["profile"]
@@ -231,10 +243,10 @@ def lbfgs_roofline(prob, cfg, r, peaks):
 
 def workload_line(name, items, warmup, steps, peaks, roofline=True):
     log(f"{name}: {len(items)} problem(s), {sum(c.N for _, c, _ in items)} samples, {steps} timed cycle(s)")
-    r = run_gpu(items, warmup, steps)
+    r = run_gpu(items, warmup, steps, profile_steps=steps)
     si = nominal_si(items) * steps
     out = dict(workload=name, ms_per_step=r["seconds"] / steps * 1e3, value=si / r["seconds"],
-               active_value=active_si(items, r) / r["seconds"], unit="sample-iterations/s", cycles=steps,
+               active_value=si / r["seconds"] * active_fraction(items, r), unit="sample-iterations/s", cycles=steps,
                kernel_ms_per_step={k: round(v["ms"] / steps, 3) for k, v in r["profile"].items() if v["launches"]})
     if roofline:
         out["roofline"] = eval_roofline(items, r, peaks, dominant_only=len(items) == 1)
@@ -373,6 +385,8 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--profile-steps", type=int, default=5,
+                    help="cycles after the timed ones, launched one by one with HIP events (kernel times, rooflines)")
     ap.add_argument("--fd-steps", type=int, default=1, help="finite-difference cycles timed (0: skip)")
     ap.add_argument("--N", type=int, default=65536)
     ap.add_argument("--cpu-samples", type=int, default=2048, help="oracle baseline sample size (0: skip the oracle leg)")
@@ -414,17 +428,17 @@ def main(argv=None):
     items = [(prob, cfg, x0)]
     si_per_cycle = nominal_si(items)
     log(f"adjoint: N={cfg.N} d={prob.d} K={prob.K} warmup={args.warmup} steps={args.steps}")
-    adj = run_gpu(items, args.warmup, args.steps)
+    adj = run_gpu(items, args.warmup, args.steps, profile_steps=args.profile_steps)
     value = si_per_cycle * args.steps / adj["seconds"]
     ms_per_step = adj["seconds"] / args.steps * 1e3
-    active = active_si(items, adj) / adj["seconds"]
+    active = value * active_fraction(items, adj)
     log(f"adjoint: {ms_per_step:.1f} ms/cycle, {value:.4g} sample-iterations/s ({active:.4g} active)")
 
     fd = None
     if args.fd_steps > 0:
         log(f"finite differences: {args.fd_steps} cycle(s) from the same start")
         fitems = [(prob, cfg.with_(grad_mode=0), x0)]
-        r = run_gpu(fitems, 0, args.fd_steps, profile=False)
+        r = run_gpu(fitems, 0, args.fd_steps)
         fd_value = si_per_cycle * args.fd_steps / r["seconds"]
         adj_first = adj["warmup_seconds"][0] if adj["warmup_seconds"] else None
         fd = dict(value=fd_value, unit="sample-iterations/s", cycles=args.fd_steps,
@@ -434,7 +448,7 @@ def main(argv=None):
 
     roof = eval_roofline(items, adj, peaks)
     roof_lbfgs = lbfgs_roofline(prob, cfg, adj, peaks)
-    kernel_ms = {k: round(v["ms"] / args.steps, 3) for k, v in adj["profile"].items() if v["launches"]}
+    kernel_ms = {k: round(v["ms"] / args.profile_steps, 3) for k, v in adj["profile"].items() if v["launches"]}
 
     others = {}
     if args.batch_steps > 0:

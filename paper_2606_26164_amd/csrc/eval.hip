@@ -674,6 +674,8 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
                                 gacc[1][i] *= sc1;
                             }
                         }
+                    }
+                    if constexpr (GRAD) {
                         float pw0, pw1;
                         rows_pair_split(pk * w, pw0, pw1);
 #pragma unroll
@@ -724,7 +726,7 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
                     }
                 }
             };
-            const int K = pd.K;
+            const int K = __builtin_amdgcn_readfirstlane(pd.K);
             const int wvu = __builtin_amdgcn_readfirstlane(wv);
             const int kb = SPLIT == 1 ? 0 : (wvu * K) / SPLIT, ke = SPLIT == 1 ? K : ((wvu + 1) * K) / SPLIT;
             if constexpr (DP < 64) {
