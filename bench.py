@@ -33,7 +33,20 @@ import time
 
 METRIC = "sample-iterations/s at d=64,N=65536 (adjoint vs FD grad); mode recall vs oracle"
 PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_FP32_VECTOR_TFLOPS = 157.3  # 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2 (packed) x 2.4 GHz
 PEAK_HBM_GBS = 8000.0
+ALU_DP = 8  # mixtures with d <= 8 are evaluated on the VALU, one point per lane
+
+
+def padded_width(d: int) -> int:
+    """The launch class's width: 8 for the VALU path, else d padded to 16, 32 or 64."""
+    return ALU_DP if d <= ALU_DP else (16 if d <= 16 else (32 if d <= 32 else 64))
+
+
+def executed_width(d: int) -> int:
+    """Coordinates a point's arithmetic runs over: 2, 4 or 8 on the VALU path,
+    the padded tile width otherwise."""
+    return (2 if d <= 2 else (4 if d <= 4 else 8)) if d <= ALU_DP else padded_width(d)
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 PROFILES = os.path.join(HERE, "profiles")
@@ -204,21 +217,23 @@ def eval_roofline(items, r, peaks, dominant_only=True):
         flops = padded = 0
         for cyc in r["stats"]:
             for (prob, _, _), s in zip(items, cyc):
-                dp = 16 if prob.d <= 16 else (32 if prob.d <= 32 else 64)
                 flops += s["evals"] * eval_flops_per_point(prob.d, prob.K)
-                padded += s["evals"] * eval_flops_per_point(dp, prob.K)
+                padded += s["evals"] * eval_flops_per_point(executed_width(prob.d), prob.K)
         ev = [k for k in prof if k.startswith("eval")]
         ms = sum(prof[k]["ms"] for k in ev)
         launches = sum(prof[k]["launches"] for k in ev)
         kernel, traffic = "eval_kernel (all launch kinds)", None
         extra = dict(achieved_padded=padded / (ms * 1e-3) / 1e12,
-                     note="achieved counts each problem's own d; achieved_padded the MFMA work at the padded "
-                          "width (16, 32 or 64) the tiles execute")
+                     note="achieved counts each problem's own d; achieved_padded the work at the width the "
+                          "kernel executes (tiles padded to 16, 32 or 64; 2, 4 or 8 on the VALU path)")
     achieved = flops / (ms * 1e-3) / 1e12
-    out = dict(bound="mfma", achieved=achieved, peak=PEAK_FP32_MFMA_TFLOPS, unit="TFLOP/s",
-               frac=achieved / PEAK_FP32_MFMA_TFLOPS, traffic=traffic, traffic_unit="bytes per launch",
+    # mixtures with d <= 8 run on the VALU, the rest on the FP32 matrix cores
+    alu = all(padded_width(prob.d) == ALU_DP for prob, _, _ in items)
+    peak = PEAK_FP32_VECTOR_TFLOPS if alu else PEAK_FP32_MFMA_TFLOPS
+    out = dict(bound="alu" if alu else "mfma", achieved=achieved, peak=peak, unit="TFLOP/s",
+               frac=achieved / peak, traffic=traffic, traffic_unit="bytes per launch",
                kernel=kernel, launches=launches, avg_launch_ms=ms / max(launches, 1))
-    if peaks:
+    if peaks and not alu:
         out.update(peak_measured=peaks["fp32_mfma_tflops"], frac_measured=achieved / peaks["fp32_mfma_tflops"])
     out.update(extra)
     return out
@@ -255,14 +270,14 @@ def workload_line(name, items, warmup, steps, peaks, roofline=True):
 
 
 def batch_class_lines(W, peaks, steps):
-    """The 64-problem batch by evaluation launch class (padded width 16, 32,
-    64): each class's problems in a handle of their own (a class's launches are
-    the same launches in the full batch), so each class gets its own
-    roofline."""
+    """The 64-problem batch by evaluation launch class (width 8 on the VALU,
+    16, 32, 64 on the matrix cores): each class's problems in a handle of their
+    own (a class's launches are the same launches in the full batch), so each
+    class gets its own roofline."""
     items = W.batch64()
     out = {}
-    for dp in (16, 32, 64):
-        sub = [it for it in items if (16 if it[0].d <= 16 else (32 if it[0].d <= 32 else 64)) == dp]
+    for dp in (ALU_DP, 16, 32, 64):
+        sub = [it for it in items if padded_width(it[0].d) == dp]
         if sub:
             out[f"padded_d{dp}"] = workload_line(f"batch class padded d={dp} ({len(sub)} problems)", sub, 1, steps,
                                                  peaks)

@@ -316,7 +316,7 @@ const char *chisao_last_error(void);
  * 1024 workgroups. The schedule changes timing only, never results. */
 #define CHISAO_TUNE_VARIANTS 4
 typedef struct {
-    int32_t padded_d;    /* 16, 32 or 64 */
+    int32_t padded_d;    /* 8 (mixtures with d <= 8, evaluated one point per lane), 16, 32 or 64 */
     int32_t family;
     int32_t grad_mode;
     int32_t n_problems;  /* problems in the class */

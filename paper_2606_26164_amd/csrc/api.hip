@@ -60,8 +60,6 @@ struct Buffers {
     }
 };
 
-int pad_dim(int d) { return d <= 16 ? 16 : (d <= 32 ? 32 : 64); }
-
 // Launch schedules the autotuner tries per evaluation class: tile order
 // (linear, XCD-chunked) x grid (8192 workgroups, dispatched as slots free up;
 // 1024, one resident wave per SIMD looping over tiles).
@@ -281,7 +279,7 @@ extern "C" int chisao_init_batched(chisao_handle *out, int n_problems, const chi
         std::vector<int> order(P);
         for (int p = 0; p < n_problems; ++p) order[p] = p;
         auto key = [&](int p) {
-            return std::make_tuple(pad_dim(ps[p].d), ps[p].family, cs[p].grad_mode);
+            return std::make_tuple(pad_dim(ps[p].d, ps[p].family), ps[p].family, cs[p].grad_mode);
         };
         std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key(a) < key(b); });
         std::vector<int> s0_of(P);
@@ -299,7 +297,7 @@ extern "C" int chisao_init_batched(chisao_handle *out, int n_problems, const chi
             const chisao_config &c = cs[p];
             // closed-form functions have no component arrays
             const bool closed = pr.family >= CHISAO_RASTRIGIN;
-            const size_t d = pr.d, K = closed ? 0 : pr.K, DP = pad_dim(pr.d);
+            const size_t d = pr.d, K = closed ? 0 : pr.K, DP = pad_dim(pr.d, pr.family);
             ProblemDesc &q = h->pdh[p];
             memset(&q, 0, sizeof q);
             float *Pfrag = nullptr, *muB = nullptr, *logc2 = nullptr, *lo, *hi;
@@ -1177,7 +1175,7 @@ extern "C" int chisao_eval_static(const chisao_problem *p, float fd_h, const flo
     if (grad_mode != CHISAO_GRAD_FD && grad_mode != CHISAO_GRAD_ADJOINT) return fail(CHISAO_E_INVAL, "bad grad_mode");
     if (!isfinite(fd_h)) return fail(CHISAO_E_INVAL, "non-finite fd_h");
     const bool closed = p->family >= CHISAO_RASTRIGIN;
-    const size_t d = p->d, K = closed ? 0 : p->K, DP = pad_dim(p->d);
+    const size_t d = p->d, K = closed ? 0 : p->K, DP = pad_dim(p->d, p->family);
     // scratch layout: descriptors, then the tables, each section 256-byte aligned
     size_t used = 0;
     auto take = [&](size_t bytes) {

@@ -12,6 +12,21 @@ constexpr int kWave = 64;
 // objective families from here on are closed-form test functions
 constexpr int kFamClosed = CHISAO_RASTRIGIN;
 
+// Evaluation width.  Mixtures with d <= 8 run on the VALU, one lane per
+// point (padded width kAluDP); larger d, and the closed forms, run in tiles
+// padded to 16, 32 or 64 coordinates.
+constexpr int kAluDP = 8;
+__host__ __device__ constexpr int pad_dim(int d, int family) {
+    return (family < kFamClosed && d <= kAluDP) ? kAluDP : (d <= 16 ? 16 : (d <= 32 ? 32 : 64));
+}
+// Within the VALU path a problem's components are W = 2, 4 or 8 wide and
+// stored as one record each: the upper triangle of P_k row by row
+// (W (W + 1) / 2 values), then mu_k (W), then log2 of weight times
+// normaliser, padded to a multiple of four floats.  At most 48 floats, so a
+// record table fits the K * 8 * 8 floats of a width-8 fragment table.
+__host__ __device__ constexpr int alu_width(int d) { return d <= 2 ? 2 : (d <= 4 ? 4 : 8); }
+__host__ __device__ constexpr int alu_record(int W) { return (W * (W + 1) / 2 + W + 1 + 3) / 4 * 4; }
+
 // ---------------------------------------------------------------------------
 // Counter-based random streams: Philox4x32-10 (Salmon, Moraes, Dror, Shaw,
 // SC'11), ten rounds with the Weyl key schedule.  The counter words are
@@ -149,8 +164,9 @@ __host__ __device__ inline float ordered_to_float(int i) {
 struct ProblemDesc {
     int d, DP, K, family;
     float nu, nu_plus_d;
-    const float *Pfrag;  // [K][DP/4][64][DP/16] MFMA A-operand fragments of the precision matrices
-    const float *muB;    // [K][4][DP/4]  centre coordinates in B-operand lane order
+    const float *Pfrag;  // [K][DP/4][64][DP/16] MFMA A-operand fragments of the precision matrices;
+                         // at DP = kAluDP the component records [K][alu_record(W)] instead
+    const float *muB;    // [K][4][DP/4]  centre coordinates in B-operand lane order (unused at DP = kAluDP)
     const float *logc2;  // [K] log2 of weight times normaliser
     const float *lo, *hi;
     int N, s0;

@@ -35,8 +35,8 @@ namespace chisao {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 
-constexpr int NB = 2;    // 16-point blocks per wave
-constexpr int PPW = 32;  // points per wave
+constexpr int NB = 2;          // 16-point blocks per wave
+constexpr int kTilePts = 32;  // points per wave in the MFMA tiles
 using AllBlocks = std::integral_constant<int, NB>;
 using OneBlock = std::integral_constant<int, 1>;
 constexpr float kLog2e = 1.4426950408889634f;
@@ -51,6 +51,15 @@ typedef const float __attribute__((address_space(1))) gfloat;
 typedef const f32x4 __attribute__((address_space(1))) gf32x4;
 typedef const f32x2 __attribute__((address_space(1))) gf32x2;
 __device__ __forceinline__ const gfloat *as_global(const float *p) { return (const gfloat *)p; }
+// A read-only table whose address is the same in every lane, in the constant
+// address space: loads at wave-uniform offsets compile to scalar loads.
+typedef const float __attribute__((address_space(4))) cfloat;
+__device__ __forceinline__ const cfloat *uniform_const(const float *p) {
+    const uint64_t a = reinterpret_cast<uint64_t>(p);
+    const uint64_t u = (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)a) |
+                       ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(a >> 32)) << 32);
+    return reinterpret_cast<const cfloat *>(u);
+}
 
 template <int MB>
 __device__ __forceinline__ void load_frag(const gfloat *p, float out[MB]) {
@@ -215,7 +224,7 @@ constexpr int kMaxClass = 256;  // problems per class (LDS budget: 2 waves per S
 // is one tile's pass over the components, which four waves share; the closed
 // forms have no component loop to split
 template <int DP, int FAM>
-constexpr int trial_split() { return FAM < kFamClosed ? 4 : 1; }
+constexpr int trial_split() { return (FAM < kFamClosed && DP != kAluDP) ? 4 : 1; }
 
 __device__ __forceinline__ int job_count(const EvalArgs &a, int p, const ProblemDesc &pd) {
     if (a.ext_n >= 0) return a.ext_n;
@@ -273,6 +282,9 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
     constexpr int KS = DP / 4;
     constexpr int MB = DP / 16;
     constexpr bool CLOSED = FAM >= kFamClosed;
+    // small mixtures: one lane per point on the VALU, 64 points per tile
+    constexpr bool ALU = !CLOSED && DP == kAluDP;
+    constexpr int PPW = ALU ? kWave : kTilePts;
     constexpr int LD = DP + 1;  // padded row: conflict-free column reads
     constexpr int NP = SPLIT > 1 ? SPLIT - 1 : 1;
     __shared__ float s_pm[NP][NB][kWave], s_ps[NP][NB][kWave];       // partial max / sum of waves 1..
@@ -550,6 +562,87 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
                 if constexpr (GRAD)
                     for (int c = c0; c < d; c += 2) s_g[pt * LD + c] = cf_grad(pd.family, d, x, c, sa, sb);
             }
+            __syncthreads();
+        } else if constexpr (ALU) {
+            // ---- small mixtures: one lane per point on the VALU ----------------
+            // A few coordinates give the matrix core too little to do: padded
+            // to 16, a d = 2 component would cost its full 16-wide tile.  Here
+            // each lane carries one point through the components; the tile's
+            // problem is the same in every lane, so a component's record (P's
+            // upper triangle, mu, log2 weight) is read with scalar loads and
+            // enters each instruction as its scalar operand.
+            const int W = alu_width(d);
+            const int K = __builtin_amdgcn_readfirstlane(pd.K);
+            const cfloat *tab = uniform_const(pd.Pfrag);
+            const float nu = pd.nu, nupd = pd.nu_plus_d;
+            auto run = [&](auto wc) {
+                constexpr int Wc = decltype(wc)::value, T = Wc * (Wc + 1) / 2, R = alu_record(Wc);
+                const int pt = lane;
+                float xr[Wc], ga[GRAD ? Wc : 1];
+#pragma unroll
+                for (int i = 0; i < Wc; ++i) {
+                    xr[i] = s_pts[pt * LD + i];
+                    if constexpr (GRAD) ga[i] = 0.0f;
+                }
+                float m = -INFINITY, sm = 0.0f;
+                for (int k = 0; k < K; ++k) {
+                    const cfloat *rec = tab + k * R;
+                    float dl[Wc], u[Wc];
+#pragma unroll
+                    for (int i = 0; i < Wc; ++i) dl[i] = xr[i] - rec[T + i];
+                    // u = P (x - mu) from the upper triangle, q = (x - mu) . u
+                    float q = 0.0f;
+#pragma unroll
+                    for (int i = 0; i < Wc; ++i) {
+                        float acc = 0.0f;
+#pragma unroll
+                        for (int j = 0; j < Wc; ++j) {
+                            const int lo = i < j ? i : j, hi = i < j ? j : i;
+                            acc = fmaf(rec[lo * Wc - lo * (lo - 1) / 2 + (hi - lo)], dl[j], acc);
+                        }
+                        u[i] = acc;
+                        q = fmaf(dl[i], acc, q);
+                    }
+                    float l2, w = 1.0f;
+                    if constexpr (FAM == 0) {
+                        l2 = rec[T + Wc] - q * (0.5f * kLog2e);
+                    } else {
+                        l2 = rec[T + Wc] - (0.5f * nupd * kLog2e) * log1pf(q / nu);
+                        w = nupd / (nu + q);
+                    }
+                    // the same online log-sum-exp as the tiles: the reference
+                    // moves only when a term exceeds it by 2^kLseSlack, which
+                    // few components do, so the rescale is a rare branch
+                    const bool moved = l2 > m + kLseSlack;
+                    if (__any(moved)) {
+                        const float mnew = moved ? l2 : m;
+                        const float sc = moved ? __builtin_amdgcn_exp2f(m - mnew) : 1.0f;
+                        sm *= sc;
+                        if constexpr (GRAD)
+#pragma unroll
+                            for (int i = 0; i < Wc; ++i) ga[i] *= sc;
+                        m = mnew;
+                    }
+                    const float pk = __builtin_amdgcn_exp2f(l2 - m);
+                    sm += pk;
+                    if constexpr (GRAD) {
+                        const float pw = pk * w;
+#pragma unroll
+                        for (int i = 0; i < Wc; ++i) ga[i] = fmaf(pw, u[i], ga[i]);
+                    }
+                }
+                float f = (m + __log2f(sm)) * kLn2;
+                if (noisy && s_s[pt] >= 0) f += noise_of(pt);
+                s_f[pt] = f;
+                if constexpr (GRAD) {
+                    const float inv = -1.0f / sm;
+#pragma unroll
+                    for (int i = 0; i < Wc; ++i) s_g[pt * LD + i] = ga[i] * inv;
+                }
+            };
+            if (W == 2) run(std::integral_constant<int, 2>{});
+            else if (W == 4) run(std::integral_constant<int, 4>{});
+            else run(std::integral_constant<int, 8>{});
             __syncthreads();
         } else {
             // ---- operand registers ---------------------------------------------
@@ -857,15 +950,18 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
             // Armijo margins f_tr - f - c1 g.(x_tr - x), two lanes per point
             const int DS = D.DS;
             if (lead) {
-                const int pt = lane >> 1, h = lane & 1, s = s_s[pt];
-                float dot = 0.0f;
-                if (s >= 0)
-                    for (int b = h; b < KS; b += 2) dot += s_dp[pt * KS + b];
-                dot += __shfl_xor(dot, 1, kWave);
-                // (relaxed by twice the noise level for noisy objectives: the
-                // noise-aware Armijo test of Berahas, Byrd and Nocedal 2019)
-                if (h == 0)
-                    s_pass[pt] = (s >= 0) && (s_f[pt] - D.F[s] - pd.ls_c1 * dot + 2.0f * pd.noise_sigma >= 0.0f);
+                for (int pt0 = 0; pt0 < PPW; pt0 += kWave / 2) {
+                    const int pt = pt0 + (lane >> 1), h = lane & 1, s = s_s[pt];
+                    float dot = 0.0f;
+                    if (s >= 0)
+                        for (int b = h; b < KS; b += 2) dot += s_dp[pt * KS + b];
+                    dot += __shfl_xor(dot, 1, kWave);
+                    // (relaxed by twice the noise level for noisy objectives: the
+                    // noise-aware Armijo test of Berahas, Byrd and Nocedal 2019)
+                    if (h == 0)
+                        s_pass[pt] =
+                            (s >= 0) && (s_f[pt] - D.F[s] - pd.ls_c1 * dot + 2.0f * pd.noise_sigma >= 0.0f);
+                }
             }
             __syncthreads();
             if (lead && lane < jpw) {
@@ -955,6 +1051,10 @@ hipError_t launch_eval(const EvalArgs &a, int DP, int family, int center, bool f
     : fam == 1 ? dispatch_modes<DPV, 1>(a, center, fd, grad, grid, st)                   \
                : dispatch_modes<DPV, kFamClosed>(a, center, fd, grad, grid, st)
     switch (DP) {
+        case kAluDP:  // mixtures only
+            return fam == 0   ? dispatch_modes<kAluDP, 0>(a, center, fd, grad, grid, st)
+                   : fam == 1 ? dispatch_modes<kAluDP, 1>(a, center, fd, grad, grid, st)
+                              : hipErrorInvalidValue;
         case 16: return CHISAO_FAMS(16);
         case 32: return CHISAO_FAMS(32);
         case 64: return CHISAO_FAMS(64);
@@ -966,7 +1066,8 @@ hipError_t launch_eval(const EvalArgs &a, int DP, int family, int center, bool f
 // ---------------------------------------------------------------------------
 // Per-component constants.  One workgroup per component: float64 Cholesky of
 // the precision matrix for log|P_k| (setup only), then the MFMA fragment
-// layouts.  bad[0] is set when a matrix is not positive definite.
+// layouts (or, at the VALU width, the component records).  bad[0] is set when
+// a matrix is not positive definite.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(64) void prepare_kernel(int family, int d, int DP, int K, float nu, const float *log_w,
                                                      const float *mu, const float *prec, float *logc2, float *Pfrag,
@@ -1010,6 +1111,28 @@ __global__ __launch_bounds__(64) void prepare_kernel(int family, int d, int DP, 
                 0.5 * logdet;
         }
         logc2[k] = (float)(((double)log_w[k] + c) * 1.4426950408889634);
+        if (DP == kAluDP) {
+            const int W = alu_width(d), T = W * (W + 1) / 2;
+            Pfrag[(size_t)k * alu_record(W) + T + W] = logc2[k];
+        }
+    }
+    if (DP == kAluDP) {
+        // one record per component: upper triangle of P row by row, mu, and
+        // (above) the log2 weight; coordinates past d are zero
+        const int W = alu_width(d), T = W * (W + 1) / 2, R = alu_record(W);
+        float *rec = Pfrag + (size_t)k * R;
+        for (int e = lane; e < T; e += 64) {
+            int i = 0, r = e;
+            while (r >= W - i) {
+                r -= W - i;
+                ++i;
+            }
+            const int j = i + r;
+            rec[e] = (i < d && j < d) ? A[i * d + j] : 0.0f;
+        }
+        if (lane < W) rec[T + lane] = lane < d ? mu[(size_t)k * d + lane] : 0.0f;
+        if (lane > 0 && lane < R - T - W) rec[T + W + lane] = 0.0f;
+        return;
     }
     // fragments with permuted rows: Pfrag[k][ks][lane][mb] = P[pi][4 ks + lane/16],
     // pi = 4 (4 mb + rho % 4) + rho / 4 for rho = lane % 16

@@ -171,7 +171,7 @@ def test_autotuned_schedule_changes_timing_only():
     print("\n" + "\n".join(str(t) for t in tuned))
     # classes: (padded d, family, gradient mode) of the five problems
     assert sorted((t["padded_d"], t["family"], t["grad_mode"]) for t in tuned) == \
-        [(16, 0, 0), (16, 0, 1), (16, 1, 1), (64, 0, 1)]
+        [(8, 0, 1), (8, 1, 1), (16, 0, 0), (64, 0, 1)]
     assert sum(t["n_problems"] for t in tuned) == len(items)
     for t in tuned:
         assert all(ms > 0 for ms in t["ms"])
