@@ -284,8 +284,9 @@ int chisao_eval(chisao_handle h, int problem, const float *X_dev, int B, float *
  * fragments, centres, log normalisers, descriptors) are built in a static
  * device array of 8 MiB that each GPU holds from library load to process
  * exit.  The tables take 4 (K (DP^2 + d^2 + DP + d + 2) + 2 d) bytes plus
- * about 1 KiB, DP = d rounded up to 16, 32 or 64: up to K = 251 components at
- * d = 64; a larger problem fails with CHISAO_E_RANGE and runs nothing.
+ * about 1 KiB, DP = 8 for a mixture with d <= 8, else d rounded up to 16, 32
+ * or 64: up to K = 251 components at d = 64; a larger problem fails with
+ * CHISAO_E_RANGE and runs nothing.
  * Enqueued on hip_stream (NULL = default stream) of the current device.  The
  * call synchronizes that stream once, after uploading the problem (a matrix
  * that is not positive definite fails with CHISAO_E_INVAL), and returns with

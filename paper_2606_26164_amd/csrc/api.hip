@@ -92,6 +92,12 @@ struct chisao_ctx {
     hipStream_t stream = nullptr;  // the caller's stream: all work runs here
     hipStream_t cur = nullptr;     // where launches are enqueued (stream, or the capture stream)
     hipStream_t cap = nullptr;     // private stream for graph capture
+    // side streams and events that fork the launches of several classes off
+    // `cur` and join them back (one stream per class after the first)
+    std::vector<hipStream_t> side;
+    hipEvent_t ev_fork = nullptr;
+    std::vector<hipEvent_t> ev_join;
+    std::vector<int> all_e, fd_e, all_l;  // evaluation classes, finite-difference ones, L-BFGS layouts
     int device = 0;
     int k_host = 0;  // cycles completed
     uint32_t flags = 0;
@@ -110,6 +116,9 @@ struct chisao_ctx {
         for (hipGraphExec_t g : graph)
             if (g) (void)hipGraphExecDestroy(g);
         for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+        for (hipEvent_t e : ev_join) (void)hipEventDestroy(e);
+        if (ev_fork) (void)hipEventDestroy(ev_fork);
+        for (hipStream_t s : side) (void)hipStreamDestroy(s);
         if (cap) (void)hipStreamDestroy(cap);
         buf.release();
     }
@@ -134,6 +143,31 @@ static hipError_t timed(chisao_ctx *h, int cls, F &&launch) {
     if (r != hipSuccess) return r;
     h->ev_used.push_back({cls, i});
     return hipSuccess;
+}
+
+// Enqueues body(i, stream) for each i in idx.  The launches of different
+// classes touch disjoint samples (the counters they share are updated
+// atomically), so with more than one class every class after the first goes
+// to a side stream forked from the current one and joined back: in a captured
+// cycle these are parallel branches of the graph, and the classes' launches
+// run side by side instead of one after another.  When profiling, everything
+// stays on the current stream, in order.
+template <class F>
+static hipError_t fork_join(chisao_ctx *h, const std::vector<int> &idx, F &&body) {
+    const size_t n = idx.size();
+    if (n <= 1 || h->prof || h->side.size() + 1 < n) {
+        for (int i : idx) {
+            const hipError_t e = body(i, h->cur);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+    hipError_t e = hipEventRecord(h->ev_fork, h->cur);
+    for (size_t j = 1; j < n && e == hipSuccess; ++j) e = hipStreamWaitEvent(h->side[j - 1], h->ev_fork, 0);
+    for (size_t j = 0; j < n && e == hipSuccess; ++j) e = body(idx[j], j == 0 ? h->cur : h->side[j - 1]);
+    for (size_t j = 1; j < n && e == hipSuccess; ++j) e = hipEventRecord(h->ev_join[j - 1], h->side[j - 1]);
+    for (size_t j = 1; j < n && e == hipSuccess; ++j) e = hipStreamWaitEvent(h->cur, h->ev_join[j - 1], 0);
+    return e;
 }
 
 // ---------------------------------------------------------------------------
@@ -500,6 +534,23 @@ extern "C" int chisao_init_batched(chisao_handle *out, int n_problems, const chi
             }
         }
         HIP_GO(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+        for (size_t i = 0; i < h->eclasses.size(); ++i) {
+            h->all_e.push_back((int)i);
+            if (h->eclasses[i].grad_mode != CHISAO_GRAD_ADJOINT) h->fd_e.push_back((int)i);
+        }
+        for (size_t i = 0; i < h->lclasses.size(); ++i) h->all_l.push_back((int)i);
+        {
+            const int n_side = std::max((int)h->eclasses.size(), (int)h->lclasses.size()) - 1;
+            if (n_side > 0) HIP_GO(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
+            for (int i = 0; i < n_side; ++i) {
+                hipStream_t s;
+                hipEvent_t ev;
+                HIP_GO(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+                h->side.push_back(s);
+                HIP_GO(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+                h->ev_join.push_back(ev);
+            }
+        }
         if (!(h->flags & CHISAO_FLAG_NO_AUTOTUNE) && (rc = autotune(h))) goto fail_out;
     }
 #undef ALLOC
@@ -557,12 +608,13 @@ static long tile_bound(chisao_ctx *h, const EvalClass &c, int vc_kind, bool fd, 
     return t;
 }
 
-static hipError_t run_eval(chisao_ctx *h, const EvalClass &c, EvalArgs &a, int center, bool fd, bool grad) {
+static hipError_t run_eval(chisao_ctx *h, const EvalClass &c, EvalArgs &a, int center, bool fd, bool grad,
+                           hipStream_t st) {
     a.max_tiles = tile_bound(h, c, a.vc_kind, fd, a.trial_lo, a.trial_cnt);
     a.order = c.order;
     a.grid_cap = c.grid_cap;
     const int cls = fd ? CHISAO_PROF_EVAL_FD : center;
-    return timed(h, cls, [&] { return launch_eval(a, c.DP, c.family, center, fd, grad, h->cur); });
+    return timed(h, cls, [&] { return launch_eval(a, c.DP, c.family, center, fd, grad, st); });
 }
 
 // Autotuner: per evaluation class, time each launch schedule on a value +
@@ -623,7 +675,8 @@ static int autotune(chisao_ctx *h) {
 // stencil index for the differences).
 static hipError_t eval_list(chisao_ctx *h, int list_id, float *F_out, float *G_out, bool want_f, int need_bit,
                             int step_limit, int step, uint32_t fd_base) {
-    for (const EvalClass &c : h->eclasses) {
+    return fork_join(h, h->all_e, [&](int ci, hipStream_t st) {
+        const EvalClass &c = h->eclasses[ci];
         EvalArgs a = base_args(h, c);
         a.list_id = list_id;
         a.vc_kind = kVcOne;
@@ -636,20 +689,18 @@ static hipError_t eval_list(chisao_ctx *h, int list_id, float *F_out, float *G_o
         if (c.grad_mode == CHISAO_GRAD_ADJOINT) {
             a.F_out = F_out;
             a.G_out = G_out;
-            if ((e = run_eval(h, c, a, kDirect, false, true)) != hipSuccess) return e;
-            continue;
+            return run_eval(h, c, a, kDirect, false, true, st);
         }
         if (want_f) {
             a.F_out = F_out;
             a.G_out = nullptr;
-            if ((e = run_eval(h, c, a, kDirect, false, false)) != hipSuccess) return e;
+            if ((e = run_eval(h, c, a, kDirect, false, false, st)) != hipSuccess) return e;
         }
         a.F_out = nullptr;
         a.G_out = G_out;
         a.nz_base = fd_base;
-        if ((e = run_eval(h, c, a, kDirect, true, false)) != hipSuccess) return e;
-    }
-    return hipSuccess;
+        return run_eval(h, c, a, kDirect, true, false, st);
+    });
 }
 
 static hipError_t phase_converge(chisao_ctx *h) {
@@ -664,24 +715,28 @@ static hipError_t phase_converge(chisao_ctx *h) {
         const int list_out = t % 2 ? L_T1 : L_T1B;
         if ((e = launch_reset_counts(D, (1 << list_out) | (1 << L_T2) | (1 << L_T3) | (1 << L_FD), st)) != hipSuccess)
             return e;
-        for (const LbfgsClass &lc : h->lclasses)
-            if ((e = timed(h, CHISAO_PROF_LBFGS,
-                           [&] { return launch_lbfgs_step(D, t, lc.cpl, list_in, lc.g0, lc.n, st); })) != hipSuccess)
-                return e;
+        if ((e = fork_join(h, h->all_l, [&](int li, hipStream_t ls) {
+                 const LbfgsClass &lc = h->lclasses[li];
+                 return timed(h, CHISAO_PROF_LBFGS,
+                              [&] { return launch_lbfgs_step(D, t, lc.cpl, list_in, lc.g0, lc.n, ls); });
+             })) != hipSuccess)
+            return e;
         if (t > D.n_conv_max) break;
         if ((e = launch_compact(D, list_in, list_out, -1, false, D.prof + CHISAO_PROF_LBFGS, st,
                                 D.prof + CHISAO_PROF_LBFGS_PAIRS)) != hipSuccess)
             return e;
         // first trial t = 1 for every stepper
-        for (const EvalClass &c : h->eclasses) {
-            EvalArgs a = base_args(h, c);
-            a.list_id = list_out;
-            a.vc_kind = kVcTrialFirst;
-            a.trial_next = L_T2;
-            a.step = t;
-            a.nz_kind = 0;
-            if ((e = run_eval(h, c, a, kTrial, false, c.grad_mode == CHISAO_GRAD_ADJOINT)) != hipSuccess) return e;
-        }
+        if ((e = fork_join(h, h->all_e, [&](int ci, hipStream_t es) {
+                 const EvalClass &c = h->eclasses[ci];
+                 EvalArgs a = base_args(h, c);
+                 a.list_id = list_out;
+                 a.vc_kind = kVcTrialFirst;
+                 a.trial_next = L_T2;
+                 a.step = t;
+                 a.nz_kind = 0;
+                 return run_eval(h, c, a, kTrial, false, c.grad_mode == CHISAO_GRAD_ADJOINT, es);
+             })) != hipSuccess)
+            return e;
         if ((e = launch_compact(D, list_out, L_T2, L_FD, true, nullptr, st)) != hipSuccess) return e;
         // the remaining trials in two stages: t = 1/2, 1/4, then the rest only
         // for searches that rejected those too.  Most searches that reject
@@ -689,42 +744,45 @@ static hipError_t phase_converge(chisao_ctx *h) {
         // trial at once would mostly compute points that are never used.
         for (int stage = 0; stage < 2; ++stage) {
             const int lst = stage ? L_T3 : L_T2;
-            for (const EvalClass &c : h->eclasses) {
-                EvalArgs a = base_args(h, c);
-                a.list_id = lst;
-                a.vc_kind = kVcTrialRest;
-                a.trial_lo = stage ? 3 : 1;
-                a.trial_cnt = stage ? kMaxTrials : 2;
-                a.trial_next = stage ? -1 : L_T3;
-                a.step = t;
-                a.nz_kind = 0;
-                if ((e = run_eval(h, c, a, kTrial, false, c.grad_mode == CHISAO_GRAD_ADJOINT)) != hipSuccess)
-                    return e;
-            }
+            if ((e = fork_join(h, h->all_e, [&](int ci, hipStream_t es) {
+                     const EvalClass &c = h->eclasses[ci];
+                     EvalArgs a = base_args(h, c);
+                     a.list_id = lst;
+                     a.vc_kind = kVcTrialRest;
+                     a.trial_lo = stage ? 3 : 1;
+                     a.trial_cnt = stage ? kMaxTrials : 2;
+                     a.trial_next = stage ? -1 : L_T3;
+                     a.step = t;
+                     a.nz_kind = 0;
+                     return run_eval(h, c, a, kTrial, false, c.grad_mode == CHISAO_GRAD_ADJOINT, es);
+                 })) != hipSuccess)
+                return e;
             if ((e = launch_compact(D, lst, stage ? -1 : L_T3, L_FD, true, nullptr, st)) != hipSuccess) return e;
         }
-        for (const EvalClass &c : h->eclasses) {
-            if (c.grad_mode == CHISAO_GRAD_ADJOINT) continue;
-            EvalArgs b = base_args(h, c);
-            b.list_id = L_FD;
-            b.vc_kind = kVcOne;
-            b.G_out = D.G;
-            b.step = t;
-            b.nz_kind = 0;
-            b.nz_base = kNzFd1;
-            if ((e = run_eval(h, c, b, kDirect, true, false)) != hipSuccess) return e;
-        }
+        if ((e = fork_join(h, h->fd_e, [&](int ci, hipStream_t es) {
+                 const EvalClass &c = h->eclasses[ci];
+                 EvalArgs b = base_args(h, c);
+                 b.list_id = L_FD;
+                 b.vc_kind = kVcOne;
+                 b.G_out = D.G;
+                 b.step = t;
+                 b.nz_kind = 0;
+                 b.nz_base = kNzFd1;
+                 return run_eval(h, c, b, kDirect, true, false, es);
+             })) != hipSuccess)
+            return e;
     }
     // quality-gate values of noisy problems (the other problems have no jobs)
     if (h->any_noise)
-        for (const EvalClass &c : h->eclasses) {
+        return fork_join(h, h->all_e, [&](int ci, hipStream_t es) {
+            const EvalClass &c = h->eclasses[ci];
             EvalArgs a = base_args(h, c);
             a.list_id = L_ACT;
             a.vc_kind = kVcOne;
             a.F_out = D.Fg;
             a.nz_kind = 1;
-            if ((e = run_eval(h, c, a, kDirect, false, false)) != hipSuccess) return e;
-        }
+            return run_eval(h, c, a, kDirect, false, false, es);
+        });
     return hipSuccess;
 }
 
@@ -742,18 +800,20 @@ static hipError_t phase_hlc(chisao_ctx *h) {
     if ((e = launch_sigma(D, st)) != hipSuccess) return e;
     const int n_cloud = max_over(h, &ProblemDesc::n_cloud);
     for (int step = 0; step < n_cloud; ++step) {
-        for (const EvalClass &c : h->eclasses) {
-            const bool adj = c.grad_mode == CHISAO_GRAD_ADJOINT;
-            EvalArgs a = base_args(h, c);
-            a.list_id = L_UNF;
-            a.vc_kind = kVcProbes;
-            a.step = step;
-            a.need_bit = 1 << 5;
-            a.step_limit = 1;
-            a.nz_kind = adj ? -1 : 0;
-            a.nz_base = kNzFdProbe;
-            if ((e = run_eval(h, c, a, kProbe, !adj, adj)) != hipSuccess) return e;
-        }
+        if ((e = fork_join(h, h->all_e, [&](int ci, hipStream_t es) {
+                 const EvalClass &c = h->eclasses[ci];
+                 const bool adj = c.grad_mode == CHISAO_GRAD_ADJOINT;
+                 EvalArgs a = base_args(h, c);
+                 a.list_id = L_UNF;
+                 a.vc_kind = kVcProbes;
+                 a.step = step;
+                 a.need_bit = 1 << 5;
+                 a.step_limit = 1;
+                 a.nz_kind = adj ? -1 : 0;
+                 a.nz_base = kNzFdProbe;
+                 return run_eval(h, c, a, kProbe, !adj, adj, es);
+             })) != hipSuccess)
+            return e;
         if ((e = launch_probe_mean(D, step, st)) != hipSuccess) return e;
         if (step == 0 && (e = launch_step_size(D, D.Gh, 0, st)) != hipSuccess) return e;
         if ((e = launch_hlc_update(D, step, st)) != hipSuccess) return e;

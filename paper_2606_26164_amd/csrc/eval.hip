@@ -318,12 +318,13 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
     const int g = lane >> 4, n = lane & 15;
     const bool ext = a.ext_n >= 0;
     // Tile prefix over the problems of the class.  Line-search launches are
-    // short and many, so there the first wave computes it, one problem per
-    // lane: the problems' counts are read in parallel, not one dependent load
-    // after another.  The other launches are long; there one thread walks the
-    // problems (the wave version's extra scalar registers cost the long
-    // launches' component loop more than the walk takes).
-    if constexpr (TRIAL) {
+    // short and many, and a VALU-path launch is short whatever its kind, so
+    // there the first wave computes it, one problem per lane: the problems'
+    // counts are read in parallel, not one dependent load after another.  The
+    // other launches are long; there one thread walks the problems (the wave
+    // version's extra scalar registers cost the long launches' component loop
+    // more than the walk takes).
+    if constexpr (TRIAL || ALU) {
         if (threadIdx.x < kWave) {
             int carry = 0, carry2 = 0;
             if (lane == 0) s_pref[0] = s_pref2[0] = 0;
@@ -334,7 +335,7 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
                     const int p = a.cls[j];
                     const ProblemDesc &pd = D.pd[p];
                     const int jobs = job_count(a, p, pd);
-                    const int V = centres(a, pd);
+                    const int V = centres(a, pd) * (FD ? 2 * pd.d : 1);
                     int jpw, wpj;
                     t = (int)tiles_of(jobs, V, PPW, jpw, wpj);
                     if constexpr (HALF) t2 = (int)tiles_of(jobs, V, PPW / 2, jpw, wpj);
@@ -342,7 +343,7 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
                     if (blockIdx.x == 0 && !ext && jobs > 0) {
                         const unsigned long long nv = (unsigned long long)jobs * (unsigned long long)V;
                         atomicAdd(&D.ctl[p].evals, nv);
-                        atomicAdd(&D.prof[CENTER], nv);
+                        atomicAdd(&D.prof[FD ? 3 : CENTER], nv);
                     }
                 }
                 const int inc = wave_scan(t), inc2 = HALF ? wave_scan(t2) : 0;

@@ -117,6 +117,30 @@ def test_graph_replay_equals_eager_bitwise(grad_mode):
     np.testing.assert_array_equal(out[0][2].X, out[1][2].X)
 
 
+def test_concurrent_classes_equal_serial_launches_bitwise():
+    """The launch classes of a batch run side by side (forked streams, parallel
+    graph branches); with profiling on, every launch runs in order on one
+    stream.  Both, and eager launches on the forked streams, give the same
+    bits for every problem."""
+    from paper_2606_26164_amd import _lib as L
+    from paper_2606_26164_amd.api import Optimizer
+
+    items = _mixed_batch(n_osc=3)
+    runs = {}
+    for name in ("graph", "eager", "serial"):
+        flags = L.FLAG_NO_GRAPH if name == "eager" else 0
+        with Optimizer.batched(items, flags=flags) as opt:
+            if name == "serial":
+                opt.profile_begin()
+            opt.cycle(3)
+            if name == "serial":
+                opt.profile_end()
+            runs[name] = [_state(opt, p) for p in range(len(items))]
+    for name in ("eager", "serial"):
+        for p in range(len(items)):
+            _assert_same(runs["graph"][p], runs[name][p], f"problem {p}, graph vs {name}")
+
+
 def test_graph_replay_deterministic_across_handles():
     from paper_2606_26164_amd.api import Optimizer
 
