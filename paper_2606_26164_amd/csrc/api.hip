@@ -722,8 +722,9 @@ static hipError_t phase_converge(chisao_ctx *h) {
              })) != hipSuccess)
             return e;
         if (t > D.n_conv_max) break;
-        if ((e = launch_compact(D, list_in, list_out, -1, false, D.prof + CHISAO_PROF_LBFGS, st,
-                                D.prof + CHISAO_PROF_LBFGS_PAIRS)) != hipSuccess)
+        // (the L-BFGS step and history-pair tallies are kept only when profiling)
+        if ((e = launch_compact(D, list_in, list_out, -1, false, h->prof ? D.prof + CHISAO_PROF_LBFGS : nullptr, st,
+                                h->prof ? D.prof + CHISAO_PROF_LBFGS_PAIRS : nullptr)) != hipSuccess)
             return e;
         // first trial t = 1 for every stepper
         if ((e = fork_join(h, h->all_e, [&](int ci, hipStream_t es) {

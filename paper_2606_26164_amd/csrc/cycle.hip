@@ -152,8 +152,12 @@ __global__ __launch_bounds__(kBlock) void compact_kernel(Dev D, int src, int dst
     __shared__ int s_pmin;
     __shared__ int s_wc[3][kWavesPerBlock];
     __shared__ int s_base[3];
+    // profile tallies, summed over the block and added to memory once at the
+    // end: one counter hit by every wave of a large population serializes
+    __shared__ unsigned long long s_tally, s_pairs;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
     const unsigned long long below = (1ull << lane) - 1ull;
+    if (tid == 0) s_tally = s_pairs = 0ull;
     for (int b = blockIdx.x * kBlock; b < D.NT; b += gridDim.x * kBlock) {
         const int j = b + tid;
         int p = 0, v = 0, s = -1;
@@ -188,7 +192,7 @@ __global__ __launch_bounds__(kBlock) void compact_kernel(Dev D, int src, int dst
                     const int dst = tid == 0 ? dst1 : (tid == 1 ? dst2 : -1);
                     if (dst >= 0) base = atomicAdd(&D.ctl[pl].count[dst], tot);
                     else if (tid == 2 && count_fail) atomicAdd(&D.ctl[pl].ls_fail, tot);
-                    if (tid == 0 && tally) atomicAdd(tally, (unsigned long long)tot);
+                    if (tid == 0 && tally) s_tally += (unsigned long long)tot;
                 }
                 s_base[tid] = base;
             }
@@ -205,12 +209,15 @@ __global__ __launch_bounds__(kBlock) void compact_kernel(Dev D, int src, int dst
             if (tally_pairs) {
                 float cnt = (mine && v == 1) ? (float)D.cnt[s] : 0.0f;
                 cnt = wave_sum(cnt);
-                if (lane == 0 && cnt > 0.0f) atomicAdd(tally_pairs, (unsigned long long)cnt);
+                if (lane == 0 && cnt > 0.0f) atomicAdd(&s_pairs, (unsigned long long)cnt);
             }
             pending = pending && !mine;
             __syncthreads();
         }
     }
+    __syncthreads();
+    if (tid == 0 && tally && s_tally) atomicAdd(tally, s_tally);
+    if (tid == 0 && tally_pairs && s_pairs) atomicAdd(tally_pairs, s_pairs);
 }
 
 hipError_t launch_compact(const Dev &D, int src, int dst1, int dst2, bool count_fail, unsigned long long *tally,
