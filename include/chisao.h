@@ -136,6 +136,9 @@ typedef struct {
  * anchor through the centre to the opposite anchor: a bound coordinate is
  * lo + t (hi - lo) or hi - t (hi - lo), a middle one lo + (hi - lo) / 2. */
 #define CHISAO_FLAG_RAY_SEEDING 4u
+/* Direct evaluations of matrix-core classes in 16-point tiles whatever the
+ * autotuner measures (its other tile size; results are the same). */
+#define CHISAO_FLAG_HALF_TILES 8u
 
 /* Per-cycle statistics (host struct). */
 typedef struct {
@@ -314,7 +317,10 @@ const char *chisao_last_error(void);
  * stencil pass (finite-difference classes). It keeps the default (variant 0)
  * unless another is at least 3% faster than the best so far: variant v uses
  * tile order v % 2 (0 linear, 1 XCD-chunked) and a grid of 8192 (v < 2) or
- * 1024 workgroups. The schedule changes timing only, never results. */
+ * 1024 workgroups.  Then, for an adjoint mixture class on the matrix cores,
+ * it times the value + gradient pass in tiles of 16 points instead of 32 under
+ * the chosen schedule and keeps them for direct evaluations if at least 3%
+ * faster.  Schedule and tile size change timing only, never results. */
 #define CHISAO_TUNE_VARIANTS 4
 typedef struct {
     int32_t padded_d;    /* 8 (mixtures with d <= 8, evaluated one point per lane), 16, 32 or 64 */
@@ -324,6 +330,8 @@ typedef struct {
     int32_t order;       /* chosen tile order */
     int32_t grid_cap;    /* chosen grid size */
     float ms[CHISAO_TUNE_VARIANTS]; /* measured time per variant (0 when not tuned) */
+    int32_t tile_points;            /* points per tile of direct evaluations: 32 or 16 (64 at width 8) */
+    float ms_half_tiles;            /* measured time of the pass in 16-point tiles (0 when not tried) */
 } chisao_tuning_entry;
 
 /* Writes one entry per class (at most cap) and the class count to *n_out;

@@ -14,6 +14,7 @@ GRAD_FD, GRAD_ADJOINT = 0, 1
 FLAG_NO_GRAPH = 1
 FLAG_NO_AUTOTUNE = 2
 FLAG_RAY_SEEDING = 4
+FLAG_HALF_TILES = 8
 TUNE_VARIANTS = 4
 
 
@@ -53,7 +54,7 @@ class State(C.Structure):
 class TuningEntry(C.Structure):
     _fields_ = [("padded_d", C.c_int32), ("family", C.c_int32), ("grad_mode", C.c_int32),
                 ("n_problems", C.c_int32), ("order", C.c_int32), ("grid_cap", C.c_int32),
-                ("ms", C.c_float * 4)]
+                ("ms", C.c_float * 4), ("tile_points", C.c_int32), ("ms_half_tiles", C.c_float)]
 
 
 class Peaks(C.Structure):

@@ -144,7 +144,8 @@ class Optimizer:
         n = C.c_int(0)
         L.check(self.lib.chisao_tuning(self.h, arr, 64, C.byref(n)), "chisao_tuning")
         return [dict(padded_d=e.padded_d, family=e.family, grad_mode=e.grad_mode, n_problems=e.n_problems,
-                     order=e.order, grid_cap=e.grid_cap, ms=list(e.ms)) for e in arr[:n.value]]
+                     order=e.order, grid_cap=e.grid_cap, ms=list(e.ms), tile_points=e.tile_points,
+                     ms_half_tiles=e.ms_half_tiles) for e in arr[:n.value]]
 
     def run_phases(self, mask: int):
         L.check(self.lib.chisao_run_phases(self.h, mask), "chisao_run_phases")

@@ -78,7 +78,9 @@ struct EvalClass {
     const int *pids_dev;  // into the handle's class table
     std::vector<int> pids;
     int order = 0, grid_cap = 0;  // launch schedule (set by the autotuner)
+    int half = 0;                 // 16-point tiles for direct launches (set by the autotuner)
     float tune_ms[kTuneVariants] = {};
+    float tune_half_ms = 0.0f;
 };
 // The problems of one lane layout of the L-BFGS kernel: their samples are a
 // contiguous global range [g0, g0 + n).
@@ -552,6 +554,8 @@ extern "C" int chisao_init_batched(chisao_handle *out, int n_problems, const chi
             }
         }
         if (!(h->flags & CHISAO_FLAG_NO_AUTOTUNE) && (rc = autotune(h))) goto fail_out;
+        if (h->flags & CHISAO_FLAG_HALF_TILES)
+            for (EvalClass &c : h->eclasses) c.half = (c.DP != kAluDP && c.family < kFamClosed) ? 1 : 0;
     }
 #undef ALLOC
 #undef HIP_GO
@@ -613,6 +617,7 @@ static hipError_t run_eval(chisao_ctx *h, const EvalClass &c, EvalArgs &a, int c
     a.max_tiles = tile_bound(h, c, a.vc_kind, fd, a.trial_lo, a.trial_cnt);
     a.order = c.order;
     a.grid_cap = c.grid_cap;
+    a.half_tiles = (center == kDirect && !fd) ? c.half : 0;
     const int cls = fd ? CHISAO_PROF_EVAL_FD : center;
     return timed(h, cls, [&] { return launch_eval(a, c.DP, c.family, center, fd, grad, st); });
 }
@@ -620,8 +625,11 @@ static hipError_t run_eval(chisao_ctx *h, const EvalClass &c, EvalArgs &a, int c
 // Autotuner: per evaluation class, time each launch schedule on a value +
 // gradient pass over every sample of the class's problems (the starting
 // population; F and G are recomputed by the first cycle) and keep the
-// fastest.  Every schedule computes the same tiles, so results do not depend
-// on the choice.
+// fastest; then, for matrix-core classes with the adjoint gradient, time the
+// direct launches in half tiles (16 points, one MFMA column block) under that
+// schedule.  A class whose launches hold few full tiles leaves SIMDs idle,
+// and half tiles double the waves.  Every point's arithmetic is the same in
+// every schedule and tile size, so results do not depend on the choice.
 static int autotune(chisao_ctx *h) {
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
@@ -663,6 +671,28 @@ static int autotune(chisao_ctx *h) {
         }
         c.order = kTuneOrder[best_v];
         c.grid_cap = kTuneCap[best_v];
+        if (rc != CHISAO_OK || !adj || c.DP == kAluDP || c.family >= kFamClosed) continue;
+        EvalArgs a = base_args(h, c);
+        a.vc_kind = kVcOne;
+        a.F_out = h->D.F;
+        a.G_out = h->D.G;
+        a.max_tiles = tile_bound(h, c, kVcOne, false);
+        a.order = c.order;
+        a.grid_cap = c.grid_cap;
+        a.half_tiles = 1;
+        hipError_t e = launch_eval(a, c.DP, c.family, kDirect, false, true, h->stream);  // warm-up
+        if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
+        for (int r = 0; r < 2 && e == hipSuccess; ++r) e = launch_eval(a, c.DP, c.family, kDirect, false, true, h->stream);
+        if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+            rc = fail(CHISAO_E_DEVICE, "autotuning launch failed: %s", hipGetErrorString(e));
+            break;
+        }
+        c.tune_half_ms = ms / 2.0f;
+        c.half = c.tune_half_ms < kTuneMargin * best ? 1 : 0;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -1155,6 +1185,8 @@ extern "C" int chisao_tuning(chisao_handle h, chisao_tuning_entry *out, int cap,
         o.order = c.order;
         o.grid_cap = c.grid_cap > 0 ? c.grid_cap : 8192;
         for (int v = 0; v < CHISAO_TUNE_VARIANTS; ++v) o.ms[v] = v < kTuneVariants ? c.tune_ms[v] : 0.0f;
+        o.tile_points = c.DP == kAluDP ? kWave : (c.half ? 16 : 32);
+        o.ms_half_tiles = c.tune_half_ms;
     }
     return CHISAO_OK;
 }

@@ -277,7 +277,7 @@ constexpr int kHalfTileMax = 128;
 // in wave order, then runs the epilogue.  Line-search launches are small (a
 // few thousand points), so their time is the latency of one tile's pass over
 // all K components; splitting the components cuts that latency.
-template <int DP, int FAM, bool GRAD, int CENTER, bool FD, int SPLIT>
+template <int DP, int FAM, bool GRAD, int CENTER, bool FD, int SPLIT, bool HT = false>
 __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2))) void eval_kernel(EvalArgs a) {
     constexpr int KS = DP / 4;
     constexpr int MB = DP / 16;
@@ -307,6 +307,9 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
     // half tiles: only split line-search tiles, whose launches are latency-bound
     static_assert(!(TRIAL && FD), "line-search trials take no finite differences");
     constexpr bool HALF = TRIAL && SPLIT > 1;
+    // HT: half tiles throughout (direct evaluations; the autotuner's choice
+    // for classes whose launches hold too few full tiles to fill the chip)
+    static_assert(!HT || (CENTER == kDirect && !FD && SPLIT == 1 && !CLOSED && !ALU), "half tiles: direct MFMA only");
     __shared__ int s_pref2[HALF ? kMaxClass + 1 : 1];  // tile prefix in half tiles
     __shared__ float s_x0[TRIAL ? PPW * LD : 1];
     __shared__ float s_g0[TRIAL ? PPW * LD : 1];
@@ -366,7 +369,7 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
             const int Vs = FD ? 2 * pd.d : 1;
             const int jobs = job_count(a, p, pd);
             int jpw, wpj;
-            acc += (int)tiles_of(jobs, centres(a, pd) * Vs, PPW, jpw, wpj);
+            acc += (int)tiles_of(jobs, centres(a, pd) * Vs, HT ? PPW / 2 : PPW, jpw, wpj);
             s_pref[j + 1] = acc;
             // evaluation counts, once per launch (block 0) rather than per tile
             if (blockIdx.x == 0 && !ext && jobs > 0) {
@@ -378,7 +381,7 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
         if (blockIdx.x == 0 && pts) atomicAdd(&D.prof[FD ? 3 : CENTER], pts);
     }
     __syncthreads();
-    const int ppw = HALF ? s_ppw : PPW;
+    const int ppw = HALF ? s_ppw : (HT ? PPW / 2 : PPW);
     const int *pref = (HALF && ppw < PPW) ? s_pref2 : s_pref;
     const int n_tiles = pref[a.n_cls];
 
@@ -846,6 +849,8 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
                 if constexpr (HALF) {
                     if (ppw < PPW) run(OneBlock{});
                     else run(AllBlocks{});
+                } else if constexpr (HT) {
+                    run(OneBlock{});
                 } else {
                     run(AllBlocks{});
                 }
@@ -860,6 +865,8 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
                 if constexpr (HALF) {
                     if (ppw < PPW) run(OneBlock{});
                     else run(AllBlocks{});
+                } else if constexpr (HT) {
+                    run(OneBlock{});
                 } else {
                     run(AllBlocks{});
                 }
@@ -900,7 +907,7 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
             // ---- results to LDS --------------------------------------------
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) {
-                if (!lead || (HALF && nb * 16 >= ppw)) break;
+                if (!lead || ((HALF || HT) && nb * 16 >= ppw)) break;
                 const int pt = nb * 16 + n;
                 float f = (mrun[nb] + __log2f(srun[nb])) * kLn2;
                 if (noisy && g == 0 && s_s[pt] >= 0) f += noise_of(pt);
@@ -1018,12 +1025,19 @@ template <int DP, int FAM>
 static hipError_t dispatch_modes(const EvalArgs &a, int center, bool fd, bool grad, dim3 grid, hipStream_t st) {
     const dim3 block(kWave);
 #define CHISAO_GO(C, G, F) hipLaunchKernelGGL((eval_kernel<DP, FAM, G, C, F, 1>), grid, block, 0, st, a)
+#define CHISAO_GO_HALF(G) hipLaunchKernelGGL((eval_kernel<DP, FAM, G, kDirect, false, 1, true>), grid, block, 0, st, a)
 #define CHISAO_GO_SPLIT(C, G, F)                                                                       \
     hipLaunchKernelGGL((eval_kernel<DP, FAM, G, C, F, trial_split<DP, FAM>()>), grid, dim3(kWave * trial_split<DP, FAM>()), 0, \
                        st, a)
+    constexpr bool kHalfOk = FAM < kFamClosed && DP != kAluDP;  // tiles of two MFMA column blocks
     if (center == kDirect) {
         if (fd) CHISAO_GO(kDirect, false, true);
-        else if (grad) CHISAO_GO(kDirect, true, false);
+        else if (kHalfOk && a.half_tiles) {
+            if constexpr (kHalfOk) {
+                if (grad) CHISAO_GO_HALF(true);
+                else CHISAO_GO_HALF(false);
+            }
+        } else if (grad) CHISAO_GO(kDirect, true, false);
         else CHISAO_GO(kDirect, false, false);
     } else if (center == kTrial) {
         if (grad) CHISAO_GO_SPLIT(kTrial, true, false);
@@ -1033,6 +1047,7 @@ static hipError_t dispatch_modes(const EvalArgs &a, int center, bool fd, bool gr
         else CHISAO_GO(kProbe, true, false);
     }
 #undef CHISAO_GO
+#undef CHISAO_GO_HALF
 #undef CHISAO_GO_SPLIT
     return hipGetLastError();
 }
@@ -1041,7 +1056,9 @@ hipError_t launch_eval(const EvalArgs &a, int DP, int family, int center, bool f
     if (a.max_tiles <= 0 || a.n_cls <= 0) return hipSuccess;
     if (a.n_cls > kMaxClass) return hipErrorInvalidValue;
     const long cap = a.grid_cap > 0 ? a.grid_cap : 8192;
-    long g = a.max_tiles < cap ? a.max_tiles : cap;
+    // max_tiles counts 32-point tiles; half tiles are twice as many
+    const long tiles = (center == kDirect && !fd && a.half_tiles) ? 2 * a.max_tiles : a.max_tiles;
+    long g = tiles < cap ? tiles : cap;
     if (a.order == 1) g = (g + 7) / 8 * 8;  // whole rounds over the XCDs
     const dim3 grid((unsigned)g);
     // the closed forms share one instantiation per padded dimension and

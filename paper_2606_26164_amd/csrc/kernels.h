@@ -37,6 +37,7 @@ struct EvalArgs {
     int order;            // tile order: 0 linear, 1 XCD-chunked (block b runs on XCD b % 8)
     int grid_cap;         // most workgroups launched (0: 8192); a multiple of 8 with order 1
     int nz_kind;          // evaluation noise of noisy problems: -1 none, 0 one draw per value, 1 gate mean
+    int half_tiles;       // direct value (+ gradient) launches of matrix-core classes: 16-point tiles
     uint32_t nz_base;     // noise sub-stream base (kind 0); the noise step is `step`
 };
 

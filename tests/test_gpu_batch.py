@@ -207,10 +207,39 @@ def test_autotuned_schedule_changes_timing_only():
                 best = v
         assert (t["order"], t["grid_cap"]) == (best % 2, 8192 if best < 2 else 1024)
         assert t["ms"][best] <= min(t["ms"]) / 0.97
+        # then the tile size of direct evaluations: half tiles (16 points) for
+        # adjoint matrix-core classes when at least 3% faster
+        if t["padded_d"] == 8:
+            assert (t["tile_points"], t["ms_half_tiles"]) == (64, 0)
+        elif t["grad_mode"] == L.GRAD_ADJOINT:
+            assert t["ms_half_tiles"] > 0
+            half = np.float32(t["ms_half_tiles"]) < np.float32(0.97) * np.float32(t["ms"][best])
+            assert t["tile_points"] == (16 if half else 32)
+        else:
+            assert (t["tile_points"], t["ms_half_tiles"]) == (32, 0)
     for t in fixed:
         assert (t["order"], t["grid_cap"]) == (0, 8192) and all(ms == 0 for ms in t["ms"])
+        assert t["tile_points"] == (64 if t["padded_d"] == 8 else 32) and t["ms_half_tiles"] == 0
     for p in range(len(items)):
         _assert_same(out[0][0][p], out[1][0][p], f"problem {p}: tuned vs default schedule")
+
+
+def test_half_tiles_equal_full_tiles_bitwise():
+    """Direct evaluations in 16-point tiles (one MFMA column block) give the
+    same bits as in 32-point tiles, for every problem of the mixed batch."""
+    from paper_2606_26164_amd import _lib as L
+    from paper_2606_26164_amd.api import Optimizer
+
+    items = _mixed_batch(n_osc=3)
+    out = []
+    for flags in (L.FLAG_NO_AUTOTUNE, L.FLAG_NO_AUTOTUNE | L.FLAG_HALF_TILES):
+        with Optimizer.batched(items, flags=flags) as opt:
+            tiles = sorted((t["padded_d"], t["grad_mode"], t["tile_points"]) for t in opt.tuning())
+            opt.cycle(3)
+            out.append([_state(opt, p) for p in range(len(items))])
+    assert tiles == [(8, 1, 64), (8, 1, 64), (16, 0, 16), (64, 1, 16)]
+    for p in range(len(items)):
+        _assert_same(out[0][p], out[1][p], f"problem {p}: half vs full tiles")
 
 
 def test_batched_closed_forms_equal_single_bitwise():
