@@ -44,6 +44,11 @@ constexpr float kLn2 = 0.6931471805599453f;
 // online log-sum-exp: headroom (log2) a term may exceed the running reference
 // before the reference moves
 constexpr float kLseSlack = 8.0f;
+// Student-t kernel in base 2: log2(1 + q / nu) with the hardware log2.
+// Rounding 1 + q / nu costs at most 2^-24 absolute in the argument, i.e.
+// 1.7e-7 in the log, which the factor (nu + d) / 2 scales to a few 1e-6:
+// well inside the FP32 error of the quadratic form itself.
+__device__ __forceinline__ float student_log2(float q, float inv_nu) { return __log2f(fmaf(q, inv_nu, 1.0f)); }
 
 // Pointers into the global address space (plain loads through them compile
 // to global_load, which only the vector-memory counter tracks).
@@ -578,7 +583,7 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
             const int W = alu_width(d);
             const int K = __builtin_amdgcn_readfirstlane(pd.K);
             const cfloat *tab = uniform_const(pd.Pfrag);
-            const float nu = pd.nu, nupd = pd.nu_plus_d;
+            const float nu = pd.nu, nupd = pd.nu_plus_d, inv_nu = 1.0f / nu;
             auto run = [&](auto wc) {
                 constexpr int Wc = decltype(wc)::value, T = Wc * (Wc + 1) / 2, R = alu_record(Wc);
                 const int pt = lane;
@@ -611,8 +616,8 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
                     if constexpr (FAM == 0) {
                         l2 = rec[T + Wc] - q * (0.5f * kLog2e);
                     } else {
-                        l2 = rec[T + Wc] - (0.5f * nupd * kLog2e) * log1pf(q / nu);
-                        w = nupd / (nu + q);
+                        l2 = rec[T + Wc] - (0.5f * nupd) * student_log2(q, inv_nu);
+                        w = nupd * __builtin_amdgcn_rcpf(nu + q);
                     }
                     // the same online log-sum-exp as the tiles: the reference
                     // moves only when a term exceeds it by 2^kLseSlack, which
@@ -675,7 +680,7 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
             // come through buffer loads, which only the vector-memory counter
             // tracks: flat loads would also count against the LDS counter, and
             // the cross-lane reductions of the epilogue would then wait for them.
-            const float nu = pd.nu, nupd = pd.nu_plus_d;
+            const float nu = pd.nu, nupd = pd.nu_plus_d, inv_nu = 1.0f / nu;
             CompRegs<KS, MB> ra;
             // Buffer loads: a scalar resource per table and the component's
             // byte offset in a scalar register, each lane's fixed offset in a
@@ -751,8 +756,8 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
                     if constexpr (FAM == 0) {
                         l2 = r.lc2 - q * (0.5f * kLog2e);
                     } else {
-                        l2 = r.lc2 - (0.5f * nupd * kLog2e) * log1pf(q / nu);
-                        w = nupd / (nu + q);
+                        l2 = r.lc2 - (0.5f * nupd) * student_log2(q, inv_nu);
+                        w = nupd * __builtin_amdgcn_rcpf(nu + q);
                     }
                     const bool moved = l2 > m_own + kLseSlack;
                     const float mnew = moved ? l2 : m_own;
@@ -797,8 +802,8 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
                     if constexpr (FAM == 0) {
                         l2 = r.lc2 - q * (0.5f * kLog2e);
                     } else {
-                        l2 = r.lc2 - (0.5f * nupd * kLog2e) * log1pf(q / nu);
-                        w = nupd / (nu + q);
+                        l2 = r.lc2 - (0.5f * nupd) * student_log2(q, inv_nu);
+                        w = nupd * __builtin_amdgcn_rcpf(nu + q);
                     }
                     // the reference moves only when a term exceeds it by more
                     // than 2^kLseSlack: terms stay below 2^kLseSlack, and the

@@ -39,9 +39,14 @@ def _points(prob, n, seed):
 
 
 CASES = [
+    # d <= 8: one point per lane on the VALU (widths 2, 4, 8)
     (1, 1, W.GAUSS),
     (2, 4, W.GAUSS),
+    (3, 6, W.STUDENT_T),
     (5, 3, W.GAUSS),
+    (7, 9, W.STUDENT_T),
+    (8, 40, W.GAUSS),
+    # d > 8: MFMA tiles of width 16, 32, 64
     (16, 32, W.GAUSS),
     (20, 7, W.STUDENT_T),
     (33, 5, W.GAUSS),
@@ -62,7 +67,7 @@ def _value_bound(f, Xd, op):
 @pytest.mark.parametrize("d,K,fam", CASES)
 def test_adjoint_value_and_gradient_match_oracle(d, K, fam):
     prob = W.mixture_problem(100 + d + K, d, K, 5.0, lam_range=(0.1, 1.0), family=fam, nu=3.0)
-    X = _points(prob, 1000, d)  # 1000 points: 31 full 32-point tiles and a ragged tail
+    X = _points(prob, 1000, d)  # 1000 points: 31 full 32-point tiles (15 of 64 at d <= 8) and a ragged tail
     opt = _opt(prob)
     f_gpu, G_gpu = opt.eval(torch.from_numpy(X).cuda())
     f_gpu, G_gpu = f_gpu.cpu().numpy().astype(np.float64), G_gpu.cpu().numpy().astype(np.float64)
@@ -88,7 +93,8 @@ def test_adjoint_value_and_gradient_match_oracle(d, K, fam):
     assert np.quantile(rel, 0.99) < 1e-4, np.quantile(rel, 0.99)
 
 
-@pytest.mark.parametrize("d,K,fam", [(2, 4, W.GAUSS), (16, 32, W.GAUSS), (33, 5, W.STUDENT_T), (64, 128, W.GAUSS)])
+@pytest.mark.parametrize("d,K,fam", [(2, 4, W.GAUSS), (6, 7, W.STUDENT_T), (16, 32, W.GAUSS), (33, 5, W.STUDENT_T),
+                                     (64, 128, W.GAUSS)])
 def test_fd_gradient_matches_oracle_fd(d, K, fam):
     """Both sides use h_j = 2^-8 max(1,|x_j|) and divide by the realised
     (x+h)-(x-h); they differ only by FP32 rounding of the two values:
@@ -109,8 +115,9 @@ def test_fd_gradient_matches_oracle_fd(d, K, fam):
     assert np.all(err <= bound), f"worst FD error {err.max():.3g}"
 
 
-def test_value_only_and_fd_value_agree_with_adjoint_value():
-    prob = W.mixture_problem(7, 64, 16, 5.0, lam_range=(0.1, 1.0))
+@pytest.mark.parametrize("d", [5, 64])
+def test_value_only_and_fd_value_agree_with_adjoint_value(d):
+    prob = W.mixture_problem(7, d, 16, 5.0, lam_range=(0.1, 1.0))
     X = torch.from_numpy(_points(prob, 97, 5)).cuda()
     opt = _opt(prob)
     f1, _ = opt.eval(X, grad_mode=1)
