@@ -220,9 +220,13 @@ int chisao_init(chisao_handle *out, const chisao_problem *p, const chisao_config
 /* Several independent problems in one handle (one per entry of ps/cs, up to
  * 256, uneven d, K and N allowed, equal n_osc): every kernel of a cycle covers
  * all problems, and each problem computes exactly what it would compute in a
- * handle of its own.  x0_dev: array of n_problems device pointers (entries may
- * be NULL), or NULL for uniform draws.  Problem indices below refer to the
- * order of ps. */
+ * handle of its own.  Problems are grouped into launch classes (see
+ * chisao_tuning); with several classes, each class after the first runs its
+ * evaluation and L-BFGS launches on a library-owned stream forked from
+ * hip_stream by an event and joined back to it, so the classes run side by
+ * side and everything stays ordered on hip_stream as seen by the caller.
+ * x0_dev: array of n_problems device pointers (entries may be NULL), or NULL
+ * for uniform draws.  Problem indices below refer to the order of ps. */
 int chisao_init_batched(chisao_handle *out, int n_problems, const chisao_problem *ps, const chisao_config *cs,
                         const float *const *x0_dev, void *hip_stream);
 
