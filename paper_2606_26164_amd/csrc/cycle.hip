@@ -359,7 +359,7 @@ __global__ __launch_bounds__(kBlock) void lbfgs_step_kernel(Dev D, int t, int li
                 if (accepted) {
                     code |= (uint8_t)(stt & 0x0F);
                     if (sy > pd.curv_eps * sqrtf(ss) * sqrtf(yy) && sy != 0.0f) {
-                        head = (head + 1) % m;
+                        head = head + 1 == m ? 0 : head + 1;
                         const size_t slot = ((size_t)s * mx + head) * DS;
                         row_store<CPL>(D.S + slot, d, c0, true, sv);
                         row_store<CPL>(D.Y + slot, d, c0, true, yv);
@@ -401,14 +401,17 @@ __global__ __launch_bounds__(kBlock) void lbfgs_step_kernel(Dev D, int t, int li
         const int cnt_go = go ? cnt : 0;
         const int cmax = (int)wave_max((float)cnt_go);
         float hs[MM][CPL], hy[MM][CPL], rh[MM], al[MM];
+        // the sample's ring of pairs: one 64-bit base per row, 32-bit slot
+        // offsets (slot j back from head wraps once: j < cnt <= m)
+        const size_t hb = (size_t)(go ? s : 0) * mx;
+        const float *Sb = D.S + hb * DS, *Yb = D.Y + hb * DS, *Rb = D.rho + hb;
 #pragma unroll
         for (int j = 0; j < MM; ++j) {
             const bool ok = go && j < cnt;
-            const int slot = (head - j + m) % m;
-            const size_t off = ((size_t)(ok ? s : 0) * mx + slot) * DS;
-            row_load<CPL>(D.S + off, d, c0, ok, hs[j]);
-            row_load<CPL>(D.Y + off, d, c0, ok, hy[j]);
-            rh[j] = ok ? D.rho[(size_t)s * mx + slot] : 0.0f;
+            const int slot = ok ? (head >= j ? head - j : head - j + m) : 0;
+            row_load<CPL>(Sb + slot * DS, d, c0, ok, hs[j]);
+            row_load<CPL>(Yb + slot * DS, d, c0, ok, hy[j]);
+            rh[j] = ok ? Rb[slot] : 0.0f;
         }
         float q[CPL];
 #pragma unroll
