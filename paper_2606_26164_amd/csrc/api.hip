@@ -314,8 +314,12 @@ extern "C" int chisao_init_batched(chisao_handle *out, int n_problems, const chi
         // contiguous range of samples.
         std::vector<int> order(P);
         for (int p = 0; p < n_problems; ++p) order[p] = p;
+        // Within a class the problems go in decreasing order of K (a tile's
+        // time grows with its components), so the longest tiles are dealt
+        // out first and the short ones fill in behind them.
         auto key = [&](int p) {
-            return std::make_tuple(pad_dim(ps[p].d, ps[p].family), ps[p].family, cs[p].grad_mode);
+            const int K = ps[p].family >= CHISAO_RASTRIGIN ? 0 : ps[p].K;
+            return std::make_tuple(pad_dim(ps[p].d, ps[p].family), ps[p].family, cs[p].grad_mode, -K);
         };
         std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return key(a) < key(b); });
         std::vector<int> s0_of(P);
