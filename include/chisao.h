@@ -318,13 +318,18 @@ const char *chisao_last_error(void);
  * classes by (padded d, family, gradient mode); for each class the autotuner
  * times CHISAO_TUNE_VARIANTS schedules over the starting population, on a
  * value + adjoint gradient pass (adjoint classes) or a central-difference
- * stencil pass (finite-difference classes). It keeps the default (variant 0)
- * unless another is at least 3% faster than the best so far: variant v uses
+ * stencil pass (finite-difference classes): each variant once untimed, then
+ * two rounds over the variants, a variant's time its fastest launch.  It
+ * keeps the default (variant 0) unless another is at least 3% faster than the
+ * best so far: variant v uses
  * tile order v % 2 (0 linear, 1 XCD-chunked) and a grid of 8192 (v < 2) or
  * 1024 workgroups.  Then, for an adjoint mixture class on the matrix cores,
- * it times the value + gradient pass in tiles of 16 points instead of 32 under
- * the chosen schedule and keeps them for direct evaluations if at least 3%
- * faster.  Schedule and tile size change timing only, never results. */
+ * it times the value + gradient pass in tiles of 16 and of 32 points under
+ * the chosen schedule and keeps 16 for direct evaluations if at least 3%
+ * faster.  Last, an adjoint class times the same variants on a smoothing-probe
+ * pass (M probes per sample) and picks the probe launches' schedule by the
+ * same rule; finite-difference classes use one schedule for all launches.
+ * Schedules and tile size change timing only, never results. */
 #define CHISAO_TUNE_VARIANTS 4
 typedef struct {
     int32_t padded_d;    /* 8 (mixtures with d <= 8, evaluated one point per lane), 16, 32 or 64 */
@@ -336,6 +341,10 @@ typedef struct {
     float ms[CHISAO_TUNE_VARIANTS]; /* measured time per variant (0 when not tuned) */
     int32_t tile_points;            /* points per tile of direct evaluations: 32 or 16 (64 at width 8) */
     float ms_half_tiles;            /* measured time of the pass in 16-point tiles (0 when not tried) */
+    float ms_full_tiles;            /* ... and in 32-point tiles, timed alongside (0 when not tried) */
+    int32_t probe_order;            /* schedule of the smoothing-probe launches: tile order */
+    int32_t probe_grid_cap;         /* ... and grid size */
+    float ms_probe[CHISAO_TUNE_VARIANTS]; /* measured probe-pass time per variant (0 when not tuned) */
 } chisao_tuning_entry;
 
 /* Writes one entry per class (at most cap) and the class count to *n_out;

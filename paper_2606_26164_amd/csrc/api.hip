@@ -79,8 +79,10 @@ struct EvalClass {
     std::vector<int> pids;
     int order = 0, grid_cap = 0;  // launch schedule (set by the autotuner)
     int half = 0;                 // 16-point tiles for direct launches (set by the autotuner)
+    int p_order = 0, p_grid_cap = 0;  // schedule of the smoothing-probe launches (set by the autotuner)
     float tune_ms[kTuneVariants] = {};
-    float tune_half_ms = 0.0f;
+    float tune_half_ms = 0.0f, tune_full_ms = 0.0f;
+    float tune_probe_ms[kTuneVariants] = {};
 };
 // The problems of one lane layout of the L-BFGS kernel: their samples are a
 // contiguous global range [g0, g0 + n).
@@ -619,11 +621,43 @@ static long tile_bound(chisao_ctx *h, const EvalClass &c, int vc_kind, bool fd, 
 static hipError_t run_eval(chisao_ctx *h, const EvalClass &c, EvalArgs &a, int center, bool fd, bool grad,
                            hipStream_t st) {
     a.max_tiles = tile_bound(h, c, a.vc_kind, fd, a.trial_lo, a.trial_cnt);
-    a.order = c.order;
-    a.grid_cap = c.grid_cap;
+    a.order = center == kProbe ? c.p_order : c.order;
+    a.grid_cap = center == kProbe ? c.p_grid_cap : c.grid_cap;
     a.half_tiles = (center == kDirect && !fd) ? c.half : 0;
     const int cls = fd ? CHISAO_PROF_EVAL_FD : center;
     return timed(h, cls, [&] { return launch_eval(a, c.DP, c.family, center, fd, grad, st); });
+}
+
+// Times n launch variants of one pass: every variant once untimed (clocks
+// and caches settle, so the first variant measured is not the coldest), then
+// kTuneRounds rounds over the variants in turn, each launch between its own
+// events; a variant's time is its fastest launch.
+constexpr int kTuneRounds = 2;
+template <class F>
+static hipError_t time_variants(chisao_ctx *h, hipEvent_t e0, hipEvent_t e1, int n, F &&launch, float *ms_out) {
+    hipError_t e = hipSuccess;
+    for (int v = 0; v < n && e == hipSuccess; ++v) e = launch(v);
+    for (int v = 0; v < n; ++v) ms_out[v] = 0.0f;
+    for (int r = 0; r < kTuneRounds && e == hipSuccess; ++r)
+        for (int v = 0; v < n && e == hipSuccess; ++v) {
+            e = hipEventRecord(e0, h->stream);
+            if (e == hipSuccess) e = launch(v);
+            if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e == hipSuccess && (r == 0 || ms < ms_out[v])) ms_out[v] = ms;
+        }
+    return e;
+}
+
+// The default variant 0 stays unless another is clearly faster than the one
+// kept so far: near-ties are timing noise.
+static int pick_variant(const float *ms, int n) {
+    int best = 0;
+    for (int v = 1; v < n; ++v)
+        if (ms[v] < kTuneMargin * ms[best]) best = v;
+    return best;
 }
 
 // Autotuner: per evaluation class, time each launch schedule on a value +
@@ -632,75 +666,76 @@ static hipError_t run_eval(chisao_ctx *h, const EvalClass &c, EvalArgs &a, int c
 // fastest; then, for matrix-core classes with the adjoint gradient, time the
 // direct launches in half tiles (16 points, one MFMA column block) under that
 // schedule.  A class whose launches hold few full tiles leaves SIMDs idle,
-// and half tiles double the waves.  Every point's arithmetic is the same in
-// every schedule and tile size, so results do not depend on the choice.
+// and half tiles double the waves.  Last, adjoint classes time the four
+// schedules again on a smoothing-probe pass (M probes per sample), whose
+// launches are the largest of a cycle and can rank the schedules differently
+// (finite-difference classes keep the stencil pass's choice: a stencil probe
+// pass would take seconds).  Every point's arithmetic is the same in every
+// schedule and tile size, so results do not depend on the choice.
 static int autotune(chisao_ctx *h) {
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
-    int rc = CHISAO_OK;
+    hipError_t e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(CHISAO_E_DEVICE, "hipEventCreate: %s", hipGetErrorString(e));
+    }
     for (EvalClass &c : h->eclasses) {
         // the pass the class runs most: value and adjoint gradient, or the
         // central-difference stencils (a value-only pass is far shorter and
         // does not rank the schedules of the stencil launches)
         const bool adj = c.grad_mode == CHISAO_GRAD_ADJOINT, fd = !adj;
-        float best = 0.0f;
-        int best_v = 0;
-        for (int v = 0; v < kTuneVariants && rc == CHISAO_OK; ++v) {
-            EvalArgs a = base_args(h, c);
-            a.vc_kind = kVcOne;
-            a.F_out = adj ? h->D.F : nullptr;
-            a.G_out = h->D.G;
-            a.max_tiles = tile_bound(h, c, kVcOne, fd);
-            a.order = kTuneOrder[v];
-            a.grid_cap = kTuneCap[v];
-            hipError_t e = launch_eval(a, c.DP, c.family, kDirect, fd, adj, h->stream);  // warm-up
-            if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
-            for (int r = 0; r < 2 && e == hipSuccess; ++r) e = launch_eval(a, c.DP, c.family, kDirect, fd, adj, h->stream);
-            if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
-            if (e == hipSuccess) e = hipEventSynchronize(e1);
-            float ms = 0.0f;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-            if (e != hipSuccess) {
-                rc = fail(CHISAO_E_DEVICE, "autotuning launch failed: %s", hipGetErrorString(e));
-                break;
-            }
-            c.tune_ms[v] = ms / 2.0f;
-            // another schedule must be clearly faster than the one kept so
-            // far (the default first): near-ties are timing noise
-            if (v == 0 || c.tune_ms[v] < kTuneMargin * best) {
-                best = c.tune_ms[v];
-                best_v = v;
-            }
-        }
-        c.order = kTuneOrder[best_v];
-        c.grid_cap = kTuneCap[best_v];
-        if (rc != CHISAO_OK || !adj || c.DP == kAluDP || c.family >= kFamClosed) continue;
         EvalArgs a = base_args(h, c);
         a.vc_kind = kVcOne;
-        a.F_out = h->D.F;
+        a.F_out = adj ? h->D.F : nullptr;
         a.G_out = h->D.G;
-        a.max_tiles = tile_bound(h, c, kVcOne, false);
-        a.order = c.order;
-        a.grid_cap = c.grid_cap;
-        a.half_tiles = 1;
-        hipError_t e = launch_eval(a, c.DP, c.family, kDirect, false, true, h->stream);  // warm-up
-        if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
-        for (int r = 0; r < 2 && e == hipSuccess; ++r) e = launch_eval(a, c.DP, c.family, kDirect, false, true, h->stream);
-        if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        float ms = 0.0f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        if (e != hipSuccess) {
-            rc = fail(CHISAO_E_DEVICE, "autotuning launch failed: %s", hipGetErrorString(e));
-            break;
+        a.max_tiles = tile_bound(h, c, kVcOne, fd);
+        e = time_variants(h, e0, e1, kTuneVariants, [&](int v) {
+            a.order = kTuneOrder[v];
+            a.grid_cap = kTuneCap[v];
+            return launch_eval(a, c.DP, c.family, kDirect, fd, adj, h->stream);
+        }, c.tune_ms);
+        if (e != hipSuccess) break;
+        const int best_v = pick_variant(c.tune_ms, kTuneVariants);
+        c.order = kTuneOrder[best_v];
+        c.grid_cap = kTuneCap[best_v];
+        c.p_order = c.order;
+        c.p_grid_cap = c.grid_cap;
+        if (!adj) continue;
+        if (c.DP != kAluDP && c.family < kFamClosed) {
+            // full against half tiles under the chosen schedule
+            float ms2[2];
+            a.order = c.order;
+            a.grid_cap = c.grid_cap;
+            e = time_variants(h, e0, e1, 2, [&](int v) {
+                a.half_tiles = v;
+                return launch_eval(a, c.DP, c.family, kDirect, false, true, h->stream);
+            }, ms2);
+            if (e != hipSuccess) break;
+            c.tune_full_ms = ms2[0];
+            c.tune_half_ms = ms2[1];
+            c.half = pick_variant(ms2, 2);
         }
-        c.tune_half_ms = ms / 2.0f;
-        c.half = c.tune_half_ms < kTuneMargin * best ? 1 : 0;
+        // the probe launches: every sample of the class's problems, probe
+        // step 0 (sigma is still 0 at init: the probes sit on the samples,
+        // the work is the same); the smoothed gradients land in scratch rows
+        EvalArgs b = base_args(h, c);
+        b.vc_kind = kVcProbes;
+        b.max_tiles = tile_bound(h, c, kVcProbes, false);
+        e = time_variants(h, e0, e1, kTuneVariants, [&](int v) {
+            b.order = kTuneOrder[v];
+            b.grid_cap = kTuneCap[v];
+            return launch_eval(b, c.DP, c.family, kProbe, false, true, h->stream);
+        }, c.tune_probe_ms);
+        if (e != hipSuccess) break;
+        const int pv = pick_variant(c.tune_probe_ms, kTuneVariants);
+        c.p_order = kTuneOrder[pv];
+        c.p_grid_cap = kTuneCap[pv];
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    return rc;
+    if (e != hipSuccess) return fail(CHISAO_E_DEVICE, "autotuning launch failed: %s", hipGetErrorString(e));
+    return CHISAO_OK;
 }
 
 // value and gradient of the samples on a list: adjoint in one pass; with
@@ -1191,6 +1226,10 @@ extern "C" int chisao_tuning(chisao_handle h, chisao_tuning_entry *out, int cap,
         for (int v = 0; v < CHISAO_TUNE_VARIANTS; ++v) o.ms[v] = v < kTuneVariants ? c.tune_ms[v] : 0.0f;
         o.tile_points = c.DP == kAluDP ? kWave : (c.half ? 16 : 32);
         o.ms_half_tiles = c.tune_half_ms;
+        o.ms_full_tiles = c.tune_full_ms;
+        o.probe_order = c.p_order;
+        o.probe_grid_cap = c.p_grid_cap > 0 ? c.p_grid_cap : 8192;
+        for (int v = 0; v < CHISAO_TUNE_VARIANTS; ++v) o.ms_probe[v] = v < kTuneVariants ? c.tune_probe_ms[v] : 0.0f;
     }
     return CHISAO_OK;
 }

@@ -210,16 +210,29 @@ def test_autotuned_schedule_changes_timing_only():
         # then the tile size of direct evaluations: half tiles (16 points) for
         # adjoint matrix-core classes when at least 3% faster
         if t["padded_d"] == 8:
-            assert (t["tile_points"], t["ms_half_tiles"]) == (64, 0)
+            assert (t["tile_points"], t["ms_half_tiles"], t["ms_full_tiles"]) == (64, 0, 0)
         elif t["grad_mode"] == L.GRAD_ADJOINT:
-            assert t["ms_half_tiles"] > 0
-            half = np.float32(t["ms_half_tiles"]) < np.float32(0.97) * np.float32(t["ms"][best])
+            assert t["ms_half_tiles"] > 0 and t["ms_full_tiles"] > 0
+            half = np.float32(t["ms_half_tiles"]) < np.float32(0.97) * np.float32(t["ms_full_tiles"])
             assert t["tile_points"] == (16 if half else 32)
         else:
-            assert (t["tile_points"], t["ms_half_tiles"]) == (32, 0)
+            assert (t["tile_points"], t["ms_half_tiles"], t["ms_full_tiles"]) == (32, 0, 0)
+        # the probe launches' schedule, by the same rule on a probe pass
+        # (adjoint classes; finite-difference classes keep the stencil choice)
+        if t["grad_mode"] == L.GRAD_ADJOINT:
+            assert all(ms > 0 for ms in t["ms_probe"])
+            pb = 0
+            for v in range(1, L.TUNE_VARIANTS):
+                if np.float32(t["ms_probe"][v]) < np.float32(0.97) * np.float32(t["ms_probe"][pb]):
+                    pb = v
+            assert (t["probe_order"], t["probe_grid_cap"]) == (pb % 2, 8192 if pb < 2 else 1024)
+        else:
+            assert (t["probe_order"], t["probe_grid_cap"]) == (t["order"], t["grid_cap"])
+            assert all(ms == 0 for ms in t["ms_probe"])
     for t in fixed:
         assert (t["order"], t["grid_cap"]) == (0, 8192) and all(ms == 0 for ms in t["ms"])
-        assert t["tile_points"] == (64 if t["padded_d"] == 8 else 32) and t["ms_half_tiles"] == 0
+        assert t["tile_points"] == (64 if t["padded_d"] == 8 else 32) and t["ms_half_tiles"] == t["ms_full_tiles"] == 0
+        assert (t["probe_order"], t["probe_grid_cap"]) == (0, 8192) and all(ms == 0 for ms in t["ms_probe"])
     for p in range(len(items)):
         _assert_same(out[0][0][p], out[1][0][p], f"problem {p}: tuned vs default schedule")
 
