@@ -77,18 +77,15 @@ struct EvalClass {
     int DP, family, grad_mode;
     const int *pids_dev;  // into the handle's class table
     std::vector<int> pids;
+    int g0 = 0, n = 0;    // the class's samples: a contiguous range
+    int cpl = 1;          // L-BFGS lane layout of its largest d
+    int nconv = 0;        // most L-BFGS iterations among its problems
     int order = 0, grid_cap = 0;  // launch schedule (set by the autotuner)
     int half = 0;                 // 16-point tiles for direct launches (set by the autotuner)
     int p_order = 0, p_grid_cap = 0;  // schedule of the smoothing-probe launches (set by the autotuner)
     float tune_ms[kTuneVariants] = {};
     float tune_half_ms = 0.0f, tune_full_ms = 0.0f;
     float tune_probe_ms[kTuneVariants] = {};
-};
-// The problems of one lane layout of the L-BFGS kernel: their samples are a
-// contiguous global range [g0, g0 + n).
-struct LbfgsClass {
-    int cpl;
-    int g0, n;
 };
 
 struct chisao_ctx {
@@ -101,14 +98,13 @@ struct chisao_ctx {
     std::vector<hipStream_t> side;
     hipEvent_t ev_fork = nullptr;
     std::vector<hipEvent_t> ev_join;
-    std::vector<int> all_e, fd_e, all_l;  // evaluation classes, finite-difference ones, L-BFGS layouts
+    std::vector<int> all_e, fd_e;  // evaluation classes, finite-difference ones
     int device = 0;
     int k_host = 0;  // cycles completed
     uint32_t flags = 0;
     bool any_noise = false;
     std::vector<ProblemDesc> pdh;  // host copy of the descriptors
     std::vector<EvalClass> eclasses;
-    std::vector<LbfgsClass> lclasses;
     const int *pid_seq = nullptr;  // device [P]: 0, 1, ..., P-1
     Buffers buf;
     hipGraphExec_t graph[2] = {nullptr, nullptr};  // [0]: cycles before n_osc, [1]: the last cycle
@@ -419,10 +415,8 @@ extern "C" int chisao_init_batched(chisao_handle *out, int n_problems, const chi
         D.pid = pid_dev;
         // ---- launch classes ----
         std::map<std::tuple<int, int, int>, std::vector<int>> ecl;
-        std::map<int, std::vector<int>> lcl;
         for (int p = 0; p < n_problems; ++p) {
             ecl[{h->pdh[p].DP, h->pdh[p].family, h->pdh[p].grad_mode}].push_back(p);
-            lcl[coords_per_lane(h->pdh[p].d)].push_back(p);
         }
         std::vector<int> table;
         for (int p = 0; p < n_problems; ++p) table.push_back(p);  // pid_seq
@@ -439,19 +433,17 @@ extern "C" int chisao_init_batched(chisao_handle *out, int n_problems, const chi
             c.pids = kv.second;
             c.pids_dev = tab_dev + off;
             off += kv.second.size();
-            h->eclasses.push_back(c);
-        }
-        for (auto &kv : lcl) {
-            LbfgsClass c;
-            c.cpl = kv.first;
             c.g0 = (int)N;
-            int end = 0;
-            for (int p : kv.second) {
-                c.g0 = std::min(c.g0, h->pdh[p].s0);
-                end = std::max(end, h->pdh[p].s0 + h->pdh[p].N);
+            int dmax = 1;
+            for (int p : c.pids) {
+                const ProblemDesc &q = h->pdh[p];
+                c.g0 = std::min(c.g0, q.s0);
+                c.n += q.N;
+                dmax = std::max(dmax, q.d);
+                c.nconv = std::max(c.nconv, q.n_conv);
             }
-            c.n = end - c.g0;
-            h->lclasses.push_back(c);
+            c.cpl = coords_per_lane(dmax);
+            h->eclasses.push_back(c);
         }
         // ---- population state ----
         const size_t DSz = (size_t)DS;
@@ -546,9 +538,8 @@ extern "C" int chisao_init_batched(chisao_handle *out, int n_problems, const chi
             h->all_e.push_back((int)i);
             if (h->eclasses[i].grad_mode != CHISAO_GRAD_ADJOINT) h->fd_e.push_back((int)i);
         }
-        for (size_t i = 0; i < h->lclasses.size(); ++i) h->all_l.push_back((int)i);
         {
-            const int n_side = std::max((int)h->eclasses.size(), (int)h->lclasses.size()) - 1;
+            const int n_side = (int)h->eclasses.size() - 1;
             if (n_side > 0) HIP_GO(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
             for (int i = 0; i < n_side; ++i) {
                 hipStream_t s;
@@ -738,122 +729,129 @@ static int autotune(chisao_ctx *h) {
     return CHISAO_OK;
 }
 
-// value and gradient of the samples on a list: adjoint in one pass; with
-// finite differences the value (if wanted) and the stencil gradient.  Values
+// value and gradient of one class's samples on a list, on st: adjoint in one
+// pass; with finite differences the value (if wanted) and the stencil gradient.  Values
 // of noisy problems carry noise (sub-stream 0 for the value, fd_base plus the
 // stencil index for the differences).
+static hipError_t eval_list_class(chisao_ctx *h, const EvalClass &c, hipStream_t st, int list_id, float *F_out,
+                                  float *G_out, bool want_f, int need_bit, int step_limit, int step, uint32_t fd_base) {
+    EvalArgs a = base_args(h, c);
+    a.list_id = list_id;
+    a.vc_kind = kVcOne;
+    a.need_bit = need_bit;
+    a.step_limit = step_limit;
+    a.step = step;
+    a.nz_kind = 0;
+    a.nz_base = 0;
+    hipError_t e;
+    if (c.grad_mode == CHISAO_GRAD_ADJOINT) {
+        a.F_out = F_out;
+        a.G_out = G_out;
+        return run_eval(h, c, a, kDirect, false, true, st);
+    }
+    if (want_f) {
+        a.F_out = F_out;
+        a.G_out = nullptr;
+        if ((e = run_eval(h, c, a, kDirect, false, false, st)) != hipSuccess) return e;
+    }
+    a.F_out = nullptr;
+    a.G_out = G_out;
+    a.nz_base = fd_base;
+    return run_eval(h, c, a, kDirect, true, false, st);
+}
+
+// the same for every class, side by side
 static hipError_t eval_list(chisao_ctx *h, int list_id, float *F_out, float *G_out, bool want_f, int need_bit,
                             int step_limit, int step, uint32_t fd_base) {
     return fork_join(h, h->all_e, [&](int ci, hipStream_t st) {
-        const EvalClass &c = h->eclasses[ci];
-        EvalArgs a = base_args(h, c);
-        a.list_id = list_id;
-        a.vc_kind = kVcOne;
-        a.need_bit = need_bit;
-        a.step_limit = step_limit;
-        a.step = step;
-        a.nz_kind = 0;
-        a.nz_base = 0;
-        hipError_t e;
-        if (c.grad_mode == CHISAO_GRAD_ADJOINT) {
-            a.F_out = F_out;
-            a.G_out = G_out;
-            return run_eval(h, c, a, kDirect, false, true, st);
-        }
-        if (want_f) {
-            a.F_out = F_out;
-            a.G_out = nullptr;
-            if ((e = run_eval(h, c, a, kDirect, false, false, st)) != hipSuccess) return e;
-        }
-        a.F_out = nullptr;
-        a.G_out = G_out;
-        a.nz_base = fd_base;
-        return run_eval(h, c, a, kDirect, true, false, st);
+        return eval_list_class(h, h->eclasses[ci], st, list_id, F_out, G_out, want_f, need_bit, step_limit, step,
+                               fd_base);
     });
 }
 
-static hipError_t phase_converge(chisao_ctx *h) {
+// Phase 1 of one evaluation class, on the stream st.  The classes' problems
+// share no samples, lists or counters, so each class runs its whole L-BFGS
+// loop (for as many iterations as its problems need) without waiting for the
+// others at every stage: in a captured cycle the classes are parallel chains.
+static hipError_t converge_class(chisao_ctx *h, const EvalClass &c, hipStream_t st) {
     const Dev &D = h->D;
-    hipStream_t st = h->cur;
+    const bool adj = c.grad_mode == CHISAO_GRAD_ADJOINT;
+    const int np = (int)c.pids.size();
     hipError_t e;
-    if ((e = launch_begin_cycle(D, st)) != hipSuccess) return e;
-    if ((e = eval_list(h, L_ACT, D.F, D.G, true, 0, 0, 0, kNzFd1)) != hipSuccess) return e;
-    for (int t = 1; t <= D.n_conv_max + 1; ++t) {
+    if ((e = eval_list_class(h, c, st, L_ACT, D.F, D.G, true, 0, 0, 0, kNzFd1)) != hipSuccess) return e;
+    for (int t = 1; t <= c.nconv + 1; ++t) {
         // the steppers of iteration t go to list_out; t+1 reads them back
         const int list_in = t == 1 ? L_ACT : ((t - 1) % 2 ? L_T1 : L_T1B);
         const int list_out = t % 2 ? L_T1 : L_T1B;
-        if ((e = launch_reset_counts(D, (1 << list_out) | (1 << L_T2) | (1 << L_T3) | (1 << L_FD), st)) != hipSuccess)
+        if ((e = launch_reset_counts(D, (1 << list_out) | (1 << L_T2) | (1 << L_T3) | (1 << L_FD), st, c.pids_dev,
+                                     np)) != hipSuccess)
             return e;
-        if ((e = fork_join(h, h->all_l, [&](int li, hipStream_t ls) {
-                 const LbfgsClass &lc = h->lclasses[li];
-                 return timed(h, CHISAO_PROF_LBFGS,
-                              [&] { return launch_lbfgs_step(D, t, lc.cpl, list_in, lc.g0, lc.n, ls); });
-             })) != hipSuccess)
+        if ((e = timed(h, CHISAO_PROF_LBFGS,
+                       [&] { return launch_lbfgs_step(D, t, c.cpl, list_in, c.g0, c.n, st); })) != hipSuccess)
             return e;
-        if (t > D.n_conv_max) break;
+        if (t > c.nconv) break;
         // (the L-BFGS step and history-pair tallies are kept only when profiling)
         if ((e = launch_compact(D, list_in, list_out, -1, false, h->prof ? D.prof + CHISAO_PROF_LBFGS : nullptr, st,
-                                h->prof ? D.prof + CHISAO_PROF_LBFGS_PAIRS : nullptr)) != hipSuccess)
+                                h->prof ? D.prof + CHISAO_PROF_LBFGS_PAIRS : nullptr, c.g0, c.n)) != hipSuccess)
             return e;
         // first trial t = 1 for every stepper
-        if ((e = fork_join(h, h->all_e, [&](int ci, hipStream_t es) {
-                 const EvalClass &c = h->eclasses[ci];
-                 EvalArgs a = base_args(h, c);
-                 a.list_id = list_out;
-                 a.vc_kind = kVcTrialFirst;
-                 a.trial_next = L_T2;
-                 a.step = t;
-                 a.nz_kind = 0;
-                 return run_eval(h, c, a, kTrial, false, c.grad_mode == CHISAO_GRAD_ADJOINT, es);
-             })) != hipSuccess)
+        {
+            EvalArgs a = base_args(h, c);
+            a.list_id = list_out;
+            a.vc_kind = kVcTrialFirst;
+            a.trial_next = L_T2;
+            a.step = t;
+            a.nz_kind = 0;
+            if ((e = run_eval(h, c, a, kTrial, false, adj, st)) != hipSuccess) return e;
+        }
+        if ((e = launch_compact(D, list_out, L_T2, L_FD, true, nullptr, st, nullptr, c.g0, c.n)) != hipSuccess)
             return e;
-        if ((e = launch_compact(D, list_out, L_T2, L_FD, true, nullptr, st)) != hipSuccess) return e;
         // the remaining trials in two stages: t = 1/2, 1/4, then the rest only
         // for searches that rejected those too.  Most searches that reject
         // t = 1 accept one of the next two, so evaluating every remaining
         // trial at once would mostly compute points that are never used.
         for (int stage = 0; stage < 2; ++stage) {
             const int lst = stage ? L_T3 : L_T2;
-            if ((e = fork_join(h, h->all_e, [&](int ci, hipStream_t es) {
-                     const EvalClass &c = h->eclasses[ci];
-                     EvalArgs a = base_args(h, c);
-                     a.list_id = lst;
-                     a.vc_kind = kVcTrialRest;
-                     a.trial_lo = stage ? 3 : 1;
-                     a.trial_cnt = stage ? kMaxTrials : 2;
-                     a.trial_next = stage ? -1 : L_T3;
-                     a.step = t;
-                     a.nz_kind = 0;
-                     return run_eval(h, c, a, kTrial, false, c.grad_mode == CHISAO_GRAD_ADJOINT, es);
-                 })) != hipSuccess)
+            EvalArgs a = base_args(h, c);
+            a.list_id = lst;
+            a.vc_kind = kVcTrialRest;
+            a.trial_lo = stage ? 3 : 1;
+            a.trial_cnt = stage ? kMaxTrials : 2;
+            a.trial_next = stage ? -1 : L_T3;
+            a.step = t;
+            a.nz_kind = 0;
+            if ((e = run_eval(h, c, a, kTrial, false, adj, st)) != hipSuccess) return e;
+            if ((e = launch_compact(D, lst, stage ? -1 : L_T3, L_FD, true, nullptr, st, nullptr, c.g0, c.n)) !=
+                hipSuccess)
                 return e;
-            if ((e = launch_compact(D, lst, stage ? -1 : L_T3, L_FD, true, nullptr, st)) != hipSuccess) return e;
         }
-        if ((e = fork_join(h, h->fd_e, [&](int ci, hipStream_t es) {
-                 const EvalClass &c = h->eclasses[ci];
-                 EvalArgs b = base_args(h, c);
-                 b.list_id = L_FD;
-                 b.vc_kind = kVcOne;
-                 b.G_out = D.G;
-                 b.step = t;
-                 b.nz_kind = 0;
-                 b.nz_base = kNzFd1;
-                 return run_eval(h, c, b, kDirect, true, false, es);
-             })) != hipSuccess)
-            return e;
+        if (!adj) {
+            EvalArgs b = base_args(h, c);
+            b.list_id = L_FD;
+            b.vc_kind = kVcOne;
+            b.G_out = D.G;
+            b.step = t;
+            b.nz_kind = 0;
+            b.nz_base = kNzFd1;
+            if ((e = run_eval(h, c, b, kDirect, true, false, st)) != hipSuccess) return e;
+        }
     }
     // quality-gate values of noisy problems (the other problems have no jobs)
-    if (h->any_noise)
-        return fork_join(h, h->all_e, [&](int ci, hipStream_t es) {
-            const EvalClass &c = h->eclasses[ci];
-            EvalArgs a = base_args(h, c);
-            a.list_id = L_ACT;
-            a.vc_kind = kVcOne;
-            a.F_out = D.Fg;
-            a.nz_kind = 1;
-            return run_eval(h, c, a, kDirect, false, false, es);
-        });
+    if (h->any_noise) {
+        EvalArgs a = base_args(h, c);
+        a.list_id = L_ACT;
+        a.vc_kind = kVcOne;
+        a.F_out = D.Fg;
+        a.nz_kind = 1;
+        return run_eval(h, c, a, kDirect, false, false, st);
+    }
     return hipSuccess;
+}
+
+static hipError_t phase_converge(chisao_ctx *h) {
+    hipError_t e;
+    if ((e = launch_begin_cycle(h->D, h->cur)) != hipSuccess) return e;
+    return fork_join(h, h->all_e, [&](int ci, hipStream_t st) { return converge_class(h, h->eclasses[ci], st); });
 }
 
 static int max_over(chisao_ctx *h, int ProblemDesc::*f) {

@@ -129,15 +129,19 @@ hipError_t launch_begin_cycle(const Dev &D, hipStream_t st) {
     return launch_fill_u8(D.trace, kTrNone, (size_t)(D.n_conv_max + 1) * D.NT, st);
 }
 
-__global__ void reset_counts_kernel(Dev D, int mask) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= D.P) return;
-    for (int i = 0; i < kNumLists; ++i)
-        if (mask & (1 << i)) D.ctl[p].count[i] = 0;
+// the problems pids[0 .. np) (pids null: problems 0 .. np)
+__global__ void reset_counts_kernel(Dev D, int mask, const int *pids, int np) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= np) return;
+    const int p = pids ? pids[i] : i;
+    for (int l = 0; l < kNumLists; ++l)
+        if (mask & (1 << l)) D.ctl[p].count[l] = 0;
 }
 
-hipError_t launch_reset_counts(const Dev &D, int mask, hipStream_t st) {
-    hipLaunchKernelGGL(reset_counts_kernel, dim3(grid_for(D.P, 64)), dim3(64), 0, st, D, mask);
+hipError_t launch_reset_counts(const Dev &D, int mask, hipStream_t st, const int *pids, int np) {
+    const int n = pids ? np : D.P;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(reset_counts_kernel, dim3(grid_for(n, 64)), dim3(64), 0, st, D, mask, pids, n);
     return hipGetLastError();
 }
 
@@ -148,7 +152,8 @@ hipError_t launch_reset_counts(const Dev &D, int mask, hipStream_t st) {
 // one address serialise in the L2, which made per-wave appends the dominant
 // cost of the L-BFGS step.
 __global__ __launch_bounds__(kBlock) void compact_kernel(Dev D, int src, int dst1, int dst2, int count_fail,
-                                                         unsigned long long *tally, unsigned long long *tally_pairs) {
+                                                         unsigned long long *tally, unsigned long long *tally_pairs,
+                                                         int pos0, int pos1) {
     __shared__ int s_pmin;
     __shared__ int s_wc[3][kWavesPerBlock];
     __shared__ int s_base[3];
@@ -158,10 +163,10 @@ __global__ __launch_bounds__(kBlock) void compact_kernel(Dev D, int src, int dst
     const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
     const unsigned long long below = (1ull << lane) - 1ull;
     if (tid == 0) s_tally = s_pairs = 0ull;
-    for (int b = blockIdx.x * kBlock; b < D.NT; b += gridDim.x * kBlock) {
+    for (int b = pos0 + blockIdx.x * kBlock; b < pos1; b += gridDim.x * kBlock) {
         const int j = b + tid;
         int p = 0, v = 0, s = -1;
-        if (j < D.NT) {
+        if (j < pos1) {
             p = D.pid[j];
             if (j - D.pd[p].s0 < D.ctl[p].count[src]) {
                 v = D.flag[j];
@@ -221,9 +226,14 @@ __global__ __launch_bounds__(kBlock) void compact_kernel(Dev D, int src, int dst
 }
 
 hipError_t launch_compact(const Dev &D, int src, int dst1, int dst2, bool count_fail, unsigned long long *tally,
-                          hipStream_t st, unsigned long long *tally_pairs) {
-    hipLaunchKernelGGL(compact_kernel, dim3(grid_for(D.NT, kBlock, 4096)), dim3(kBlock), 0, st, D, src, dst1, dst2,
-                       (int)count_fail, tally, tally_pairs);
+                          hipStream_t st, unsigned long long *tally_pairs, int g0, int n) {
+    if (n < 0) {
+        g0 = 0;
+        n = D.NT;
+    }
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(compact_kernel, dim3(grid_for(n, kBlock, 4096)), dim3(kBlock), 0, st, D, src, dst1, dst2,
+                       (int)count_fail, tally, tally_pairs, g0, g0 + n);
     return hipGetLastError();
 }
 
@@ -237,7 +247,8 @@ __global__ void build_unfrozen_kernel(Dev D) {
 }
 
 hipError_t launch_build_unfrozen(const Dev &D, hipStream_t st) {
-    hipLaunchKernelGGL(reset_counts_kernel, dim3(grid_for(D.P, 64)), dim3(64), 0, st, D, 1 << L_UNF);
+    hipLaunchKernelGGL(reset_counts_kernel, dim3(grid_for(D.P, 64)), dim3(64), 0, st, D, 1 << L_UNF,
+                       (const int *)nullptr, D.P);
     hipLaunchKernelGGL(build_unfrozen_kernel, dim3(grid_for(D.NT, kBlock)), dim3(kBlock), 0, st, D);
     return hipGetLastError();
 }

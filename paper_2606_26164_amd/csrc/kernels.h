@@ -55,22 +55,25 @@ hipError_t launch_prepare(int family, int d, int DP, int K, float nu, const floa
 hipError_t launch_fill_u8(uint8_t *p, uint8_t v, size_t n, hipStream_t st);
 hipError_t launch_uniform_init(const Dev &D, hipStream_t st);
 hipError_t launch_begin_cycle(const Dev &D, hipStream_t st);
-hipError_t launch_reset_counts(const Dev &D, int mask, hipStream_t st);
+// Zero the counts of the lists in `mask` of the problems pids[0 .. np)
+// (device array), or of every problem when pids is null.
+hipError_t launch_reset_counts(const Dev &D, int mask, hipStream_t st, const int *pids = nullptr, int np = 0);
 // Stream compaction of the list `src` by D.flag: for each problem, position j
 // of src's segment (j < its count) with flag[j] == v is appended to list
 // dst[v - 1] (v = 1, 2; -1: none); positions with flag == 3 are counted into
 // the problem's ls_fail.  Entries keep ascending position order within a
 // block.  The number appended for v = 1 is added to *tally when not null, and
-// the history pair counts (D.cnt) of those samples to *tally_pairs.
+// the history pair counts (D.cnt) of those samples to *tally_pairs.  Only the
+// positions [g0, g0 + n) are scanned (n < 0: all), which must hold whole
+// problems.
 hipError_t launch_compact(const Dev &D, int src, int dst1, int dst2, bool count_fail, unsigned long long *tally,
-                          hipStream_t st, unsigned long long *tally_pairs = nullptr);
+                          hipStream_t st, unsigned long long *tally_pairs = nullptr, int g0 = 0, int n = -1);
 hipError_t launch_build_unfrozen(const Dev &D, hipStream_t st);
-// L-BFGS step over the samples listed in `samples` (nullptr: all NT), all of
-// whose problems have d <= 16 * cpl.
 // Iteration t of the L-BFGS loop for the samples on list `list_in` (all
 // active samples at t = 1, the previous iteration's steppers after), over the
-// list positions [g0, g0 + n) of the problems of one lane layout; D.flag of a
-// position is set to 1 when its sample was given a direction, else 0.
+// list positions [g0, g0 + n) of a set of whole problems, all with
+// d <= 16 cpl; D.flag of a position is set to 1 when its sample was given a
+// direction, else 0.
 hipError_t launch_lbfgs_step(const Dev &D, int t, int cpl, int list_in, int g0, int n, hipStream_t st);
 hipError_t launch_stick(const Dev &D, hipStream_t st);
 hipError_t launch_dedup(const Dev &D, hipStream_t st);
