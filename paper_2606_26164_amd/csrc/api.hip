@@ -769,89 +769,116 @@ static hipError_t eval_list(chisao_ctx *h, int list_id, float *F_out, float *G_o
     });
 }
 
-// Phase 1 of one evaluation class, on the stream st.  The classes' problems
-// share no samples, lists or counters, so each class runs its whole L-BFGS
-// loop (for as many iterations as its problems need) without waiting for the
-// others at every stage: in a captured cycle the classes are parallel chains.
-static hipError_t converge_class(chisao_ctx *h, const EvalClass &c, hipStream_t st) {
+// Iteration t of Phase 1 for one evaluation class, on the stream st (t runs
+// to the class's own n_conv + 1, which closes the last iteration).
+static hipError_t converge_iteration(chisao_ctx *h, const EvalClass &c, hipStream_t st, int t) {
     const Dev &D = h->D;
     const bool adj = c.grad_mode == CHISAO_GRAD_ADJOINT;
-    const int np = (int)c.pids.size();
     hipError_t e;
-    if ((e = eval_list_class(h, c, st, L_ACT, D.F, D.G, true, 0, 0, 0, kNzFd1)) != hipSuccess) return e;
-    for (int t = 1; t <= c.nconv + 1; ++t) {
-        // the steppers of iteration t go to list_out; t+1 reads them back
-        const int list_in = t == 1 ? L_ACT : ((t - 1) % 2 ? L_T1 : L_T1B);
-        const int list_out = t % 2 ? L_T1 : L_T1B;
-        if ((e = launch_reset_counts(D, (1 << list_out) | (1 << L_T2) | (1 << L_T3) | (1 << L_FD), st, c.pids_dev,
-                                     np)) != hipSuccess)
-            return e;
-        if ((e = timed(h, CHISAO_PROF_LBFGS,
-                       [&] { return launch_lbfgs_step(D, t, c.cpl, list_in, c.g0, c.n, st); })) != hipSuccess)
-            return e;
-        if (t > c.nconv) break;
-        // (the L-BFGS step and history-pair tallies are kept only when profiling)
-        if ((e = launch_compact(D, list_in, list_out, -1, false, h->prof ? D.prof + CHISAO_PROF_LBFGS : nullptr, st,
-                                h->prof ? D.prof + CHISAO_PROF_LBFGS_PAIRS : nullptr, c.g0, c.n)) != hipSuccess)
-            return e;
-        // first trial t = 1 for every stepper
-        {
-            EvalArgs a = base_args(h, c);
-            a.list_id = list_out;
-            a.vc_kind = kVcTrialFirst;
-            a.trial_next = L_T2;
-            a.step = t;
-            a.nz_kind = 0;
-            if ((e = run_eval(h, c, a, kTrial, false, adj, st)) != hipSuccess) return e;
-        }
-        if ((e = launch_compact(D, list_out, L_T2, L_FD, true, nullptr, st, nullptr, c.g0, c.n)) != hipSuccess)
-            return e;
-        // the remaining trials in two stages: t = 1/2, 1/4, then the rest only
-        // for searches that rejected those too.  Most searches that reject
-        // t = 1 accept one of the next two, so evaluating every remaining
-        // trial at once would mostly compute points that are never used.
-        for (int stage = 0; stage < 2; ++stage) {
-            const int lst = stage ? L_T3 : L_T2;
-            EvalArgs a = base_args(h, c);
-            a.list_id = lst;
-            a.vc_kind = kVcTrialRest;
-            a.trial_lo = stage ? 3 : 1;
-            a.trial_cnt = stage ? kMaxTrials : 2;
-            a.trial_next = stage ? -1 : L_T3;
-            a.step = t;
-            a.nz_kind = 0;
-            if ((e = run_eval(h, c, a, kTrial, false, adj, st)) != hipSuccess) return e;
-            if ((e = launch_compact(D, lst, stage ? -1 : L_T3, L_FD, true, nullptr, st, nullptr, c.g0, c.n)) !=
-                hipSuccess)
-                return e;
-        }
-        if (!adj) {
-            EvalArgs b = base_args(h, c);
-            b.list_id = L_FD;
-            b.vc_kind = kVcOne;
-            b.G_out = D.G;
-            b.step = t;
-            b.nz_kind = 0;
-            b.nz_base = kNzFd1;
-            if ((e = run_eval(h, c, b, kDirect, true, false, st)) != hipSuccess) return e;
-        }
-    }
-    // quality-gate values of noisy problems (the other problems have no jobs)
-    if (h->any_noise) {
+    // the steppers of iteration t go to list_out; t+1 reads them back
+    const int list_in = t == 1 ? L_ACT : ((t - 1) % 2 ? L_T1 : L_T1B);
+    const int list_out = t % 2 ? L_T1 : L_T1B;
+    if ((e = launch_reset_counts(D, (1 << list_out) | (1 << L_T2) | (1 << L_T3) | (1 << L_FD), st, c.pids_dev,
+                                 (int)c.pids.size())) != hipSuccess)
+        return e;
+    if ((e = timed(h, CHISAO_PROF_LBFGS,
+                   [&] { return launch_lbfgs_step(D, t, c.cpl, list_in, c.g0, c.n, st); })) != hipSuccess)
+        return e;
+    if (t > c.nconv) return hipSuccess;
+    // (the L-BFGS step and history-pair tallies are kept only when profiling)
+    if ((e = launch_compact(D, list_in, list_out, -1, false, h->prof ? D.prof + CHISAO_PROF_LBFGS : nullptr, st,
+                            h->prof ? D.prof + CHISAO_PROF_LBFGS_PAIRS : nullptr, c.g0, c.n)) != hipSuccess)
+        return e;
+    // first trial t = 1 for every stepper
+    {
         EvalArgs a = base_args(h, c);
-        a.list_id = L_ACT;
-        a.vc_kind = kVcOne;
-        a.F_out = D.Fg;
-        a.nz_kind = 1;
-        return run_eval(h, c, a, kDirect, false, false, st);
+        a.list_id = list_out;
+        a.vc_kind = kVcTrialFirst;
+        a.trial_next = L_T2;
+        a.step = t;
+        a.nz_kind = 0;
+        if ((e = run_eval(h, c, a, kTrial, false, adj, st)) != hipSuccess) return e;
+    }
+    if ((e = launch_compact(D, list_out, L_T2, L_FD, true, nullptr, st, nullptr, c.g0, c.n)) != hipSuccess) return e;
+    // the remaining trials in two stages: t = 1/2, 1/4, then the rest only
+    // for searches that rejected those too.  Most searches that reject t = 1
+    // accept one of the next two, so evaluating every remaining trial at once
+    // would mostly compute points that are never used.
+    for (int stage = 0; stage < 2; ++stage) {
+        const int lst = stage ? L_T3 : L_T2;
+        EvalArgs a = base_args(h, c);
+        a.list_id = lst;
+        a.vc_kind = kVcTrialRest;
+        a.trial_lo = stage ? 3 : 1;
+        a.trial_cnt = stage ? kMaxTrials : 2;
+        a.trial_next = stage ? -1 : L_T3;
+        a.step = t;
+        a.nz_kind = 0;
+        if ((e = run_eval(h, c, a, kTrial, false, adj, st)) != hipSuccess) return e;
+        if ((e = launch_compact(D, lst, stage ? -1 : L_T3, L_FD, true, nullptr, st, nullptr, c.g0, c.n)) !=
+            hipSuccess)
+            return e;
+    }
+    if (!adj) {
+        EvalArgs b = base_args(h, c);
+        b.list_id = L_FD;
+        b.vc_kind = kVcOne;
+        b.G_out = D.G;
+        b.step = t;
+        b.nz_kind = 0;
+        b.nz_base = kNzFd1;
+        if ((e = run_eval(h, c, b, kDirect, true, false, st)) != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
+// Phase 1.  The classes' problems share no samples, lists or counters, so
+// each class runs its whole L-BFGS loop, for as many iterations as its
+// problems need, on a stream of its own: in a captured cycle the classes are
+// parallel chains that never wait for each other (one fork before, one join
+// after).  The launches are enqueued iteration by iteration across the
+// classes, so every chain has work queued from the start.  When profiling,
+// everything runs in that order on the current stream.
 static hipError_t phase_converge(chisao_ctx *h) {
+    const Dev &D = h->D;
     hipError_t e;
-    if ((e = launch_begin_cycle(h->D, h->cur)) != hipSuccess) return e;
-    return fork_join(h, h->all_e, [&](int ci, hipStream_t st) { return converge_class(h, h->eclasses[ci], st); });
+    if ((e = launch_begin_cycle(D, h->cur)) != hipSuccess) return e;
+    const size_t n = h->eclasses.size();
+    const bool fork = n > 1 && !h->prof && h->side.size() + 1 >= n;
+    auto stream_of = [&](size_t i) { return (fork && i > 0) ? h->side[i - 1] : h->cur; };
+    if (fork) {
+        if ((e = hipEventRecord(h->ev_fork, h->cur)) != hipSuccess) return e;
+        for (size_t i = 1; i < n; ++i)
+            if ((e = hipStreamWaitEvent(h->side[i - 1], h->ev_fork, 0)) != hipSuccess) return e;
+    }
+    int tmax = 0;
+    for (size_t i = 0; i < n; ++i) {
+        const EvalClass &c = h->eclasses[i];
+        tmax = std::max(tmax, c.nconv + 1);
+        if ((e = eval_list_class(h, c, stream_of(i), L_ACT, D.F, D.G, true, 0, 0, 0, kNzFd1)) != hipSuccess) return e;
+    }
+    for (int t = 1; t <= tmax; ++t)
+        for (size_t i = 0; i < n; ++i)
+            if (t <= h->eclasses[i].nconv + 1)
+                if ((e = converge_iteration(h, h->eclasses[i], stream_of(i), t)) != hipSuccess) return e;
+    // quality-gate values of noisy problems (the other problems have no jobs)
+    if (h->any_noise)
+        for (size_t i = 0; i < n; ++i) {
+            const EvalClass &c = h->eclasses[i];
+            EvalArgs a = base_args(h, c);
+            a.list_id = L_ACT;
+            a.vc_kind = kVcOne;
+            a.F_out = D.Fg;
+            a.nz_kind = 1;
+            if ((e = run_eval(h, c, a, kDirect, false, false, stream_of(i))) != hipSuccess) return e;
+        }
+    if (fork) {
+        for (size_t i = 1; i < n; ++i)
+            if ((e = hipEventRecord(h->ev_join[i - 1], h->side[i - 1])) != hipSuccess) return e;
+        for (size_t i = 1; i < n; ++i)
+            if ((e = hipStreamWaitEvent(h->cur, h->ev_join[i - 1], 0)) != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 static int max_over(chisao_ctx *h, int ProblemDesc::*f) {
