@@ -909,7 +909,8 @@ static hipError_t phase_hlc(chisao_ctx *h) {
                  return run_eval(h, c, a, kProbe, !adj, adj, es);
              })) != hipSuccess)
             return e;
-        if ((e = launch_probe_mean(D, step, st)) != hipSuccess) return e;
+        // (the finite-difference probes' mean; adjoint probes average in the kernel)
+        if (!h->fd_e.empty() && (e = launch_probe_mean(D, step, st)) != hipSuccess) return e;
         if (step == 0 && (e = launch_step_size(D, D.Gh, 0, st)) != hipSuccess) return e;
         if ((e = launch_hlc_update(D, step, st)) != hipSuccess) return e;
     }
