@@ -145,28 +145,37 @@ static hipError_t timed(chisao_ctx *h, int cls, F &&launch) {
     return hipSuccess;
 }
 
-// Enqueues body(i, stream) for each i in idx.  The launches of different
-// classes touch disjoint samples (the counters they share are updated
-// atomically), so with more than one class every class after the first goes
-// to a side stream forked from the current one and joined back: in a captured
-// cycle these are parallel branches of the graph, and the classes' launches
-// run side by side instead of one after another.  When profiling, everything
-// stays on the current stream, in order.
+// Side streams for n classes.  The launches of different classes touch
+// disjoint samples (the counters they share are updated atomically), so with
+// more than one class every class after the first goes to a side stream
+// forked from the current one by an event and joined back by another: in a
+// captured cycle these are parallel branches of the graph, and the classes'
+// launches run side by side instead of one after another.  When profiling,
+// everything stays on the current stream, in order.
+static bool forks(const chisao_ctx *h, size_t n) { return n > 1 && !h->prof && h->side.size() + 1 >= n; }
+static hipStream_t branch(const chisao_ctx *h, bool forked, size_t j) {
+    return (forked && j > 0) ? h->side[j - 1] : h->cur;
+}
+static hipError_t fork_open(chisao_ctx *h, size_t n) {
+    hipError_t e = hipEventRecord(h->ev_fork, h->cur);
+    for (size_t j = 1; j < n && e == hipSuccess; ++j) e = hipStreamWaitEvent(h->side[j - 1], h->ev_fork, 0);
+    return e;
+}
+static hipError_t fork_close(chisao_ctx *h, size_t n) {
+    hipError_t e = hipSuccess;
+    for (size_t j = 1; j < n && e == hipSuccess; ++j) e = hipEventRecord(h->ev_join[j - 1], h->side[j - 1]);
+    for (size_t j = 1; j < n && e == hipSuccess; ++j) e = hipStreamWaitEvent(h->cur, h->ev_join[j - 1], 0);
+    return e;
+}
+
+// Enqueues body(i, stream) for each i in idx, one branch per class.
 template <class F>
 static hipError_t fork_join(chisao_ctx *h, const std::vector<int> &idx, F &&body) {
     const size_t n = idx.size();
-    if (n <= 1 || h->prof || h->side.size() + 1 < n) {
-        for (int i : idx) {
-            const hipError_t e = body(i, h->cur);
-            if (e != hipSuccess) return e;
-        }
-        return hipSuccess;
-    }
-    hipError_t e = hipEventRecord(h->ev_fork, h->cur);
-    for (size_t j = 1; j < n && e == hipSuccess; ++j) e = hipStreamWaitEvent(h->side[j - 1], h->ev_fork, 0);
-    for (size_t j = 0; j < n && e == hipSuccess; ++j) e = body(idx[j], j == 0 ? h->cur : h->side[j - 1]);
-    for (size_t j = 1; j < n && e == hipSuccess; ++j) e = hipEventRecord(h->ev_join[j - 1], h->side[j - 1]);
-    for (size_t j = 1; j < n && e == hipSuccess; ++j) e = hipStreamWaitEvent(h->cur, h->ev_join[j - 1], 0);
+    const bool forked = forks(h, n);
+    hipError_t e = forked ? fork_open(h, n) : hipSuccess;
+    for (size_t j = 0; j < n && e == hipSuccess; ++j) e = body(idx[j], branch(h, forked, j));
+    if (e == hipSuccess && forked) e = fork_close(h, n);
     return e;
 }
 
@@ -844,13 +853,9 @@ static hipError_t phase_converge(chisao_ctx *h) {
     hipError_t e;
     if ((e = launch_begin_cycle(D, h->cur)) != hipSuccess) return e;
     const size_t n = h->eclasses.size();
-    const bool fork = n > 1 && !h->prof && h->side.size() + 1 >= n;
-    auto stream_of = [&](size_t i) { return (fork && i > 0) ? h->side[i - 1] : h->cur; };
-    if (fork) {
-        if ((e = hipEventRecord(h->ev_fork, h->cur)) != hipSuccess) return e;
-        for (size_t i = 1; i < n; ++i)
-            if ((e = hipStreamWaitEvent(h->side[i - 1], h->ev_fork, 0)) != hipSuccess) return e;
-    }
+    const bool forked = forks(h, n);
+    auto stream_of = [&](size_t i) { return branch(h, forked, i); };
+    if (forked && (e = fork_open(h, n)) != hipSuccess) return e;
     int tmax = 0;
     for (size_t i = 0; i < n; ++i) {
         const EvalClass &c = h->eclasses[i];
@@ -872,13 +877,7 @@ static hipError_t phase_converge(chisao_ctx *h) {
             a.nz_kind = 1;
             if ((e = run_eval(h, c, a, kDirect, false, false, stream_of(i))) != hipSuccess) return e;
         }
-    if (fork) {
-        for (size_t i = 1; i < n; ++i)
-            if ((e = hipEventRecord(h->ev_join[i - 1], h->side[i - 1])) != hipSuccess) return e;
-        for (size_t i = 1; i < n; ++i)
-            if ((e = hipStreamWaitEvent(h->cur, h->ev_join[i - 1], 0)) != hipSuccess) return e;
-    }
-    return hipSuccess;
+    return forked ? fork_close(h, n) : hipSuccess;
 }
 
 static int max_over(chisao_ctx *h, int ProblemDesc::*f) {
