@@ -1296,6 +1296,15 @@ hipError_t launch_step_size(const Dev &D, const float *Gsrc, int which, hipStrea
     return hipGetLastError();
 }
 
+// Workgroups per problem of the element-wise update kernels (gridDim.y = P,
+// grid-stride over a problem's unfrozen rows): enough for the average
+// problem, and about 8192 in all, so a batch of many problems does not
+// dispatch thousands of workgroups per problem that find nothing to do.
+static int per_problem_blocks(const Dev &D) {
+    const int need = grid_for((long)(D.NT / D.P + 1) * D.DS, kBlock, 2048);
+    return std::max(1, std::min(need, std::max(16, 8192 / D.P)));
+}
+
 // Finite-difference smoothing: mean of the per-probe gradients, probe order.
 __global__ void probe_mean_kernel(Dev D, int step) {
     const int p = blockIdx.y;
@@ -1313,8 +1322,7 @@ __global__ void probe_mean_kernel(Dev D, int step) {
 }
 
 hipError_t launch_probe_mean(const Dev &D, int step, hipStream_t st) {
-    hipLaunchKernelGGL(probe_mean_kernel, dim3(grid_for((long)(D.NT / D.P + 1) * D.DS, kBlock, 2048), D.P),
-                       dim3(kBlock), 0, st, D, step);
+    hipLaunchKernelGGL(probe_mean_kernel, dim3(per_problem_blocks(D), D.P), dim3(kBlock), 0, st, D, step);
     return hipGetLastError();
 }
 
@@ -1334,8 +1342,7 @@ __global__ void hlc_update_kernel(Dev D, int step) {
 }
 
 hipError_t launch_hlc_update(const Dev &D, int step, hipStream_t st) {
-    hipLaunchKernelGGL(hlc_update_kernel, dim3(grid_for((long)(D.NT / D.P + 1) * D.DS, kBlock, 2048), D.P),
-                       dim3(kBlock), 0, st, D, step);
+    hipLaunchKernelGGL(hlc_update_kernel, dim3(per_problem_blocks(D), D.P), dim3(kBlock), 0, st, D, step);
     return hipGetLastError();
 }
 
@@ -1358,8 +1365,7 @@ __global__ void anti_update_kernel(Dev D, int step) {
 }
 
 hipError_t launch_anti_update(const Dev &D, int step, hipStream_t st) {
-    hipLaunchKernelGGL(anti_update_kernel, dim3(grid_for((long)(D.NT / D.P + 1) * D.DS, kBlock, 2048), D.P),
-                       dim3(kBlock), 0, st, D, step);
+    hipLaunchKernelGGL(anti_update_kernel, dim3(per_problem_blocks(D), D.P), dim3(kBlock), 0, st, D, step);
     return hipGetLastError();
 }
 
