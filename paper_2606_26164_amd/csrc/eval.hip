@@ -455,7 +455,49 @@ __global__ __launch_bounds__(64 * SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
         // rows are read in 16-byte chunks when the row stride and base allow it
         // (the library's own rows always do; a caller's array may not)
         const bool vrow = (xs & 3) == 0 && (reinterpret_cast<uintptr_t>(a.X) & 15) == 0;
-        for (int e = threadIdx.x; e < PPW * KS; e += blockDim.x) {
+        // Smoothing probes come in antithetic pairs x + sigma z, x - sigma z
+        // (centres 2i and 2i + 1 of a job).  When a job's probe count is even
+        // the two points of a pair sit side by side in the tile, from an even
+        // slot on, so one read of the sample row and one draw of z serve both
+        // (the same values the per-point loop below computes for each).
+        bool paired = false;
+        if constexpr (CENTER == kProbe && !FD) paired = (Vc & 1) == 0;
+        if (paired) {
+            for (int e = threadIdx.x; e < (PPW / 2) * KS; e += blockDim.x) {
+                const int pt = 2 * (e / KS), blk = e % KS, c0 = 4 * blk;
+                const int s = s_s[pt];  // the same sample as slot pt + 1
+                float xp[4] = {0.f, 0.f, 0.f, 0.f}, xm[4] = {0.f, 0.f, 0.f, 0.f};
+                if (s >= 0 && c0 < d) {
+                    const uint32_t pair = (uint32_t)(s_c[pt] >> 1);
+                    float z[4];
+                    box_muller4(philox((uint32_t)(s - pd.s0), kcyc, (kHLC << 24) | ((uint32_t)a.step << 16) | pair,
+                                       (uint32_t)blk, pd.key0, pd.key1),
+                                z);
+                    float xr[4] = {0.f, 0.f, 0.f, 0.f};
+                    if (vrow) {
+                        const f32x4 w = *reinterpret_cast<const f32x4 *>(a.X + (size_t)s * xs + c0);
+                        xr[0] = w[0]; xr[1] = w[1]; xr[2] = w[2]; xr[3] = w[3];
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            if (c0 + q < d) xr[q] = a.X[(size_t)s * xs + c0 + q];
+                    }
+                    const float sp = sigma, sm = -sigma;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        if (c0 + q < d) {
+                            xp[q] = xr[q] + sp * z[q];
+                            xm[q] = xr[q] + sm * z[q];
+                        }
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    s_pts[pt * LD + c0 + q] = xp[q];
+                    s_pts[(pt + 1) * LD + c0 + q] = xm[q];
+                }
+            }
+        }
+        for (int e = paired ? PPW * KS : threadIdx.x; e < PPW * KS; e += blockDim.x) {
             const int pt = e / KS, blk = e % KS, c0 = 4 * blk;
             const int s = s_s[pt];
             float x[4] = {0.f, 0.f, 0.f, 0.f};
