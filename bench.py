@@ -235,6 +235,10 @@ def eval_roofline(items, r, peaks, dominant_only=True):
                kernel=kernel, launches=launches, avg_launch_ms=ms / max(launches, 1))
     if peaks and not alu:
         out.update(peak_measured=peaks["fp32_mfma_tflops"], frac_measured=achieved / peaks["fp32_mfma_tflops"])
+    if alu:
+        # the vector peak counts packed FP32 (two lanes' worth per instruction);
+        # the build emits none, so one FMA per lane per instruction is the reachable rate
+        out.update(peak_nonpacked=PEAK_FP32_VECTOR_TFLOPS / 2, frac_nonpacked=achieved / (PEAK_FP32_VECTOR_TFLOPS / 2))
     out.update(extra)
     return out
 
