@@ -237,7 +237,8 @@ def eval_roofline(items, r, peaks, dominant_only=True):
         out.update(peak_measured=peaks["fp32_mfma_tflops"], frac_measured=achieved / peaks["fp32_mfma_tflops"])
     if alu:
         # the vector peak counts packed FP32 (two lanes' worth per instruction);
-        # the build emits none, so one FMA per lane per instruction is the reachable rate
+        # the kernels are compiled without packed FP32, so one FMA per lane per
+        # instruction is the reachable rate
         out.update(peak_nonpacked=PEAK_FP32_VECTOR_TFLOPS / 2, frac_nonpacked=achieved / (PEAK_FP32_VECTOR_TFLOPS / 2))
     out.update(extra)
     return out
@@ -422,7 +423,7 @@ def main(argv=None):
                          "traffic for hardware-counter scaling)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         return 2
     import torch
 
