@@ -4,7 +4,9 @@
 // reseeding (Phase 4), the smoothing and anti-convergence updates (Phases
 // 5-6), and the reductions that feed the data-dependent decisions.
 //
-// A launch covers every problem of the handle.  Kernels whose work is per
+// A launch covers every problem of the handle (Phase 1's L-BFGS steps, list
+// resets and compactions: the problems of one evaluation class, whose samples
+// form a contiguous range).  Kernels whose work is per
 // problem use gridDim.y = P (block (x, p) works on problem p); reductions over
 // a problem's samples use fixed block partitions of that problem and a fixed
 // combination order, so results depend neither on scheduling nor on which

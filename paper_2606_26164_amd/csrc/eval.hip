@@ -10,16 +10,20 @@
 // The same contraction therefore yields the value and its reverse-mode
 // gradient: 2 K d^2 MFMA flops per point whether or not the gradient is kept.
 //
-// Work layout: one wave per workgroup, 32 points per wave in two 16-point
-// blocks.  v_mfma_f32_16x16x4f32 computes U^T (DP x 16) = P' (DP x DP) *
+// Work layout: a tile of 32 points in two 16-point blocks per wave (direct
+// evaluations may take 16-point half tiles; four waves share a line-search
+// tile, each contracting a contiguous quarter of the components, and their
+// partial states are merged in wave order).  v_mfma_f32_16x16x4f32 computes U^T (DP x 16) = P' (DP x DP) *
 // Delta^T (DP x 16), P' the precision matrix with its rows permuted: lane l
 // supplies P[pi(16mb + l%16)][4ks + l/16] (A operand), pi(16mb + 4a + b) =
 // 4(4mb + b) + a, and delta[point l%16][4ks + l/16] (B operand), and receives
 // u at point l%16 and coordinate pi(16mb + 4(l/16) + r) = 4(4mb + r) + l/16,
 // r = 0..3.  So each lane holds u at the very coordinates it holds delta at,
 // and the quadratic form delta . u needs no second copy of delta.
-// Components are streamed; the log-sum-exp runs online in base 2 (one rescale
-// per wave only when some lane's running maximum moves).
+// Components are streamed; the log-sum-exp runs online in base 2, and its
+// reference moves (rescaling the gradient sums) only when a term exceeds it
+// by 2^kLseSlack.  Mixtures with d <= 8 take a VALU path instead, one point
+// per lane in 64-point tiles.
 //
 // The closed-form test functions of Appendix D share the kernel's tiling,
 // point generation and epilogues; their value (and analytic gradient) is a
