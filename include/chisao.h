@@ -75,7 +75,7 @@ extern "C" {
 typedef struct {
     int32_t family;      /* CHISAO_GAUSS, CHISAO_STUDENT_T or a closed form CHISAO_RASTRIGIN..CHISAO_BUKIN6 */
     int32_t d;           /* dimension, 1..64 (2 for CHISAO_BUKIN6) */
-    int32_t K;           /* number of components, >= 1 (mixtures only) */
+    int32_t K;           /* number of components, 1..65536 (mixtures only) */
     float nu;            /* Student-t degrees of freedom (> 0), ignored for Gaussians */
     const float *log_w;  /* [K] log mixture weights */
     const float *mu;     /* [K*d] component centres */

@@ -189,7 +189,8 @@ static int validate_problem(const chisao_problem *p, int idx) {
     const bool closed = p->family >= CHISAO_RASTRIGIN;
     if (p->d < 1 || p->d > 64) return fail(CHISAO_E_INVAL, "problem %d: d must be in 1..64 (got %d)", idx, p->d);
     if (p->family == CHISAO_BUKIN6 && p->d != 2) return fail(CHISAO_E_INVAL, "problem %d: Bukin N.6 needs d = 2", idx);
-    if (!closed && p->K < 1) return fail(CHISAO_E_INVAL, "problem %d: K must be >= 1", idx);
+    // (component tables are addressed with 32-bit byte offsets: K d_pad^2 4 < 2^31)
+    if (!closed && (p->K < 1 || p->K > 65536)) return fail(CHISAO_E_INVAL, "problem %d: K must be in 1..65536", idx);
     if ((!closed && (!p->log_w || !p->mu || !p->prec)) || !p->lo || !p->hi)
         return fail(CHISAO_E_INVAL, "problem %d: null problem array", idx);
     if (p->family == CHISAO_STUDENT_T && !(p->nu > 0.0f && isfinite(p->nu)))

@@ -56,7 +56,7 @@ def _bad_problem(kind):
     if kind == "d0":
         return p, c, "d must be in 1..64", lambda s: setattr(s, "d", 0)
     if kind == "K0":
-        return p, c, "K must be >= 1", lambda s: setattr(s, "K", 0)
+        return p, c, "K must be in 1..65536", lambda s: setattr(s, "K", 0)
     if kind == "box":
         lo = p.lo.copy()
         lo[2] = p.hi[2]
@@ -88,6 +88,15 @@ def test_bad_problem_is_rejected(kind):
     assert rc == L.E_INVAL
     assert h.value is None  # the output handle is cleared
     assert msg in _err()
+
+
+def test_component_count_above_65536_is_rejected():
+    p, c = _base(d=2, K=1)
+    k = 65537
+    big = W.Problem(family=W.GAUSS, d=2, K=k, log_w=np.zeros(k, np.float32), mu=np.zeros((k, 2), np.float32),
+                    prec=np.broadcast_to(np.eye(2, dtype=np.float32), (k, 2, 2)).copy(), lo=p.lo, hi=p.hi)
+    rc, _ = _init([(big, c)])
+    assert rc == L.E_INVAL and "1..65536" in _err()
 
 
 def test_dimension_above_64_is_rejected():
