@@ -244,6 +244,26 @@ def eval_roofline(items, r, peaks, dominant_only=True):
     return out
 
 
+def cycle_roofline(prob, r, peaks):
+    """Every objective evaluation of the profiled cycles (their evaluation
+    counts times the algorithmic flops per point) over those cycles' wall time
+    (launched one by one with events, a little slower than graph replay)."""
+    n = r["profile_steps"]
+    if n <= 0 or r["profile_seconds"] <= 0:
+        return None
+    evals = sum(s["evals"] for cyc in r["stats"] for s in cyc)
+    flops = evals * eval_flops_per_point(prob.d, prob.K)
+    achieved = flops / r["profile_seconds"] / 1e12
+    out = dict(bound="mfma", achieved=achieved, peak=PEAK_FP32_MFMA_TFLOPS, unit="TFLOP/s",
+               frac=achieved / PEAK_FP32_MFMA_TFLOPS, evaluations_per_cycle=evals / n,
+               ms_per_cycle=r["profile_seconds"] / n * 1e3,
+               note="every objective evaluation a cycle performs (samples, line-search trials including the "
+                    "speculative ones, smoothing probes) at K(2d^2+4d) flops each, over the whole cycle's time")
+    if peaks:
+        out.update(peak_measured=peaks["fp32_mfma_tflops"], frac_measured=achieved / peaks["fp32_mfma_tflops"])
+    return out
+
+
 def lbfgs_roofline(prob, cfg, r, peaks):
     lb = r["profile"].get("lbfgs")
     if not lb or lb["ms"] <= 0:
@@ -468,6 +488,7 @@ def main(argv=None):
 
     roof = eval_roofline(items, adj, peaks)
     roof_lbfgs = lbfgs_roofline(prob, cfg, adj, peaks)
+    cycle_roof = cycle_roofline(prob, adj, peaks)
     kernel_ms = {k: round(v["ms"] / args.profile_steps, 3) for k, v in adj["profile"].items() if v["launches"]}
 
     others = {}
@@ -545,6 +566,7 @@ def main(argv=None):
         "adjoint_over_fd": (value / fd["value"]) if fd else None,
         "roofline": roof,
         "roofline_lbfgs": roof_lbfgs,
+        "roofline_cycle": cycle_roof,
         "peaks_measured": peaks,
         "kernel_ms_per_step": kernel_ms,
         "recall": ol.get("recall"),
