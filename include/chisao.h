@@ -329,7 +329,11 @@ const char *chisao_last_error(void);
  * faster.  Last, an adjoint class times the same variants on a smoothing-probe
  * pass (M probes per sample) and picks the probe launches' schedule by the
  * same rule; finite-difference classes use one schedule for all launches.
- * Schedules and tile size change timing only, never results. */
+ * Line-search launches of matrix-core mixture classes take the chosen tile
+ * order with a grid of exactly the workgroups the GPU holds at once (the
+ * trial kernel's occupancy times the CU count), each workgroup looping over
+ * tiles; this is a rule, not a timed choice.  Schedules and tile size change
+ * timing only, never results. */
 #define CHISAO_TUNE_VARIANTS 4
 typedef struct {
     int32_t padded_d;    /* 8 (mixtures with d <= 8, evaluated one point per lane), 16, 32 or 64 */
@@ -345,6 +349,7 @@ typedef struct {
     int32_t probe_order;            /* schedule of the smoothing-probe launches: tile order */
     int32_t probe_grid_cap;         /* ... and grid size */
     float ms_probe[CHISAO_TUNE_VARIANTS]; /* measured probe-pass time per variant (0 when not tuned) */
+    int32_t trial_grid_cap;         /* grid of the line-search launches (0: the chosen grid_cap) */
 } chisao_tuning_entry;
 
 /* Writes one entry per class (at most cap) and the class count to *n_out;

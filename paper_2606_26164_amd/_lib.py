@@ -55,7 +55,8 @@ class TuningEntry(C.Structure):
     _fields_ = [("padded_d", C.c_int32), ("family", C.c_int32), ("grad_mode", C.c_int32),
                 ("n_problems", C.c_int32), ("order", C.c_int32), ("grid_cap", C.c_int32),
                 ("ms", C.c_float * 4), ("tile_points", C.c_int32), ("ms_half_tiles", C.c_float), ("ms_full_tiles", C.c_float),
-                ("probe_order", C.c_int32), ("probe_grid_cap", C.c_int32), ("ms_probe", C.c_float * 4)]
+                ("probe_order", C.c_int32), ("probe_grid_cap", C.c_int32), ("ms_probe", C.c_float * 4),
+                ("trial_grid_cap", C.c_int32)]
 
 
 class Peaks(C.Structure):

@@ -146,7 +146,7 @@ class Optimizer:
         return [dict(padded_d=e.padded_d, family=e.family, grad_mode=e.grad_mode, n_problems=e.n_problems,
                      order=e.order, grid_cap=e.grid_cap, ms=list(e.ms), tile_points=e.tile_points,
                      ms_half_tiles=e.ms_half_tiles, ms_full_tiles=e.ms_full_tiles, probe_order=e.probe_order, probe_grid_cap=e.probe_grid_cap,
-                     ms_probe=list(e.ms_probe)) for e in arr[:n.value]]
+                     ms_probe=list(e.ms_probe), trial_grid_cap=e.trial_grid_cap) for e in arr[:n.value]]
 
     def run_phases(self, mask: int):
         L.check(self.lib.chisao_run_phases(self.h, mask), "chisao_run_phases")

@@ -83,6 +83,7 @@ struct EvalClass {
     int order = 0, grid_cap = 0;  // launch schedule (set by the autotuner)
     int half = 0;                 // 16-point tiles for direct launches (set by the autotuner)
     int p_order = 0, p_grid_cap = 0;  // schedule of the smoothing-probe launches (set by the autotuner)
+    int t_grid_cap = 0;               // grid of the line-search launches: the resident workgroups (0: grid_cap)
     float tune_ms[kTuneVariants] = {};
     float tune_half_ms = 0.0f, tune_full_ms = 0.0f;
     float tune_probe_ms[kTuneVariants] = {};
@@ -453,6 +454,7 @@ extern "C" int chisao_init_batched(chisao_handle *out, int n_problems, const chi
                 c.nconv = std::max(c.nconv, q.n_conv);
             }
             c.cpl = coords_per_lane(dmax);
+            c.t_grid_cap = trial_resident_blocks(c.DP, c.family, c.grad_mode == CHISAO_GRAD_ADJOINT);
             h->eclasses.push_back(c);
         }
         // ---- population state ----
@@ -623,7 +625,11 @@ static hipError_t run_eval(chisao_ctx *h, const EvalClass &c, EvalArgs &a, int c
                            hipStream_t st) {
     a.max_tiles = tile_bound(h, c, a.vc_kind, fd, a.trial_lo, a.trial_cnt);
     a.order = center == kProbe ? c.p_order : c.order;
-    a.grid_cap = center == kProbe ? c.p_grid_cap : c.grid_cap;
+    // line-search launches: one round of resident workgroups looping over the
+    // tiles (their launches come one per stage and iteration, each a few
+    // tiles per CU; a queue of one-tile workgroups leaves a tail per launch,
+    // and in a batch it crowds out the other classes' concurrent launches)
+    a.grid_cap = center == kProbe ? c.p_grid_cap : (center == kTrial && c.t_grid_cap > 0 ? c.t_grid_cap : c.grid_cap);
     a.half_tiles = (center == kDirect && !fd) ? c.half : 0;
     const int cls = fd ? CHISAO_PROF_EVAL_FD : center;
     return timed(h, cls, [&] { return launch_eval(a, c.DP, c.family, center, fd, grad, st); });
@@ -1256,6 +1262,7 @@ extern "C" int chisao_tuning(chisao_handle h, chisao_tuning_entry *out, int cap,
         o.probe_order = c.p_order;
         o.probe_grid_cap = c.p_grid_cap > 0 ? c.p_grid_cap : 8192;
         for (int v = 0; v < CHISAO_TUNE_VARIANTS; ++v) o.ms_probe[v] = v < kTuneVariants ? c.tune_probe_ms[v] : 0.0f;
+        o.trial_grid_cap = c.t_grid_cap;
     }
     return CHISAO_OK;
 }

@@ -1103,6 +1103,37 @@ static hipError_t dispatch_modes(const EvalArgs &a, int center, bool fd, bool gr
     return hipGetLastError();
 }
 
+// Workgroups of a line-search launch resident at once on the current device
+// (the occupancy of the class's split trial kernel times the CU count), or 0
+// where line-search tiles are not split.
+template <int DP, int FAM>
+static int trial_resident(bool grad) {
+    constexpr int S = trial_split<DP, FAM>();
+    if constexpr (S == 1) {
+        return 0;
+    } else {
+        int nb = 0, dev = 0, cus = 0;
+        const hipError_t e = grad ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                                        &nb, eval_kernel<DP, FAM, true, kTrial, false, S>, kWave * S, 0)
+                                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                                        &nb, eval_kernel<DP, FAM, false, kTrial, false, S>, kWave * S, 0);
+        if (e != hipSuccess || hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return 0;
+        return nb * cus;
+    }
+}
+
+int trial_resident_blocks(int DP, int family, bool grad) {
+    if (family >= kFamClosed) return 0;
+    switch (DP) {
+        case 16: return family == 0 ? trial_resident<16, 0>(grad) : trial_resident<16, 1>(grad);
+        case 32: return family == 0 ? trial_resident<32, 0>(grad) : trial_resident<32, 1>(grad);
+        case 64: return family == 0 ? trial_resident<64, 0>(grad) : trial_resident<64, 1>(grad);
+        default: return 0;
+    }
+}
+
 hipError_t launch_eval(const EvalArgs &a, int DP, int family, int center, bool fd, bool grad, hipStream_t st) {
     if (a.max_tiles <= 0 || a.n_cls <= 0) return hipSuccess;
     if (a.n_cls > kMaxClass) return hipErrorInvalidValue;

@@ -45,6 +45,12 @@ struct EvalArgs {
 // grad: accumulate the adjoint gradient.
 hipError_t launch_eval(const EvalArgs &a, int DP, int family, int center, bool fd, bool grad, hipStream_t st);
 
+// Workgroups of a class's line-search launch that are resident at once on the
+// current GPU (0: no limit applies).  Line-search launches use that many
+// workgroups, each looping over tiles: one round of persistent workgroups
+// instead of a queue of one-tile workgroups.
+int trial_resident_blocks(int DP, int family, bool grad);
+
 // Per-component constants: log2 normalisers (float64 Cholesky of each
 // precision matrix) and the fragment layouts of the precision matrices and
 // centres.  Writes D.logc2/Pfrag/muB (device buffers passed as mutable).

@@ -229,6 +229,13 @@ def test_autotuned_schedule_changes_timing_only():
         else:
             assert (t["probe_order"], t["probe_grid_cap"]) == (t["order"], t["grid_cap"])
             assert all(ms == 0 for ms in t["ms_probe"])
+    # line-search launches of matrix-core mixture classes: one round of
+    # resident workgroups, whatever the flags (a rule, not a timed choice)
+    for t in tuned + fixed:
+        if t["padded_d"] == 8:
+            assert t["trial_grid_cap"] == 0
+        else:
+            assert t["trial_grid_cap"] > 0 and t["trial_grid_cap"] % 8 == 0
     for t in fixed:
         assert (t["order"], t["grid_cap"]) == (0, 8192) and all(ms == 0 for ms in t["ms"])
         assert t["tile_points"] == (64 if t["padded_d"] == 8 else 32) and t["ms_half_tiles"] == t["ms_full_tiles"] == 0
