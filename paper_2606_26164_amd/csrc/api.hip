@@ -99,7 +99,6 @@ struct chisao_ctx {
     std::vector<hipStream_t> side;
     hipEvent_t ev_fork = nullptr;
     std::vector<hipEvent_t> ev_join;
-    std::vector<int> all_e, fd_e;  // evaluation classes, finite-difference ones
     int device = 0;
     int k_host = 0;  // cycles completed
     uint32_t flags = 0;
@@ -166,17 +165,6 @@ static hipError_t fork_close(chisao_ctx *h, size_t n) {
     hipError_t e = hipSuccess;
     for (size_t j = 1; j < n && e == hipSuccess; ++j) e = hipEventRecord(h->ev_join[j - 1], h->side[j - 1]);
     for (size_t j = 1; j < n && e == hipSuccess; ++j) e = hipStreamWaitEvent(h->cur, h->ev_join[j - 1], 0);
-    return e;
-}
-
-// Enqueues body(i, stream) for each i in idx, one branch per class.
-template <class F>
-static hipError_t fork_join(chisao_ctx *h, const std::vector<int> &idx, F &&body) {
-    const size_t n = idx.size();
-    const bool forked = forks(h, n);
-    hipError_t e = forked ? fork_open(h, n) : hipSuccess;
-    for (size_t j = 0; j < n && e == hipSuccess; ++j) e = body(idx[j], branch(h, forked, j));
-    if (e == hipSuccess && forked) e = fork_close(h, n);
     return e;
 }
 
@@ -546,10 +534,6 @@ extern "C" int chisao_init_batched(chisao_handle *out, int n_problems, const chi
             }
         }
         HIP_GO(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
-        for (size_t i = 0; i < h->eclasses.size(); ++i) {
-            h->all_e.push_back((int)i);
-            if (h->eclasses[i].grad_mode != CHISAO_GRAD_ADJOINT) h->fd_e.push_back((int)i);
-        }
         {
             const int n_side = (int)h->eclasses.size() - 1;
             if (n_side > 0) HIP_GO(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
@@ -776,15 +760,6 @@ static hipError_t eval_list_class(chisao_ctx *h, const EvalClass &c, hipStream_t
     return run_eval(h, c, a, kDirect, true, false, st);
 }
 
-// the same for every class, side by side
-static hipError_t eval_list(chisao_ctx *h, int list_id, float *F_out, float *G_out, bool want_f, int need_bit,
-                            int step_limit, int step, uint32_t fd_base) {
-    return fork_join(h, h->all_e, [&](int ci, hipStream_t st) {
-        return eval_list_class(h, h->eclasses[ci], st, list_id, F_out, G_out, want_f, need_bit, step_limit, step,
-                               fd_base);
-    });
-}
-
 // Iteration t of Phase 1 for one evaluation class, on the stream st (t runs
 // to the class's own n_conv + 1, which closes the last iteration).
 static hipError_t converge_iteration(chisao_ctx *h, const EvalClass &c, hipStream_t st, int t) {
@@ -893,47 +868,63 @@ static int max_over(chisao_ctx *h, int ProblemDesc::*f) {
     return v;
 }
 
+// Phases 5 and 6 run as per-class chains, like Phase 1: a class's smoothing
+// (or anti-convergence) steps read and write only its own problems' samples,
+// lists and step lengths, so each class runs all of its steps on a stream of
+// its own (one fork before the steps, one join after) instead of every step
+// waiting for the slowest class.  The population statistics the steps start
+// from (the unfrozen lists, sigma) are taken before the fork.
 static hipError_t phase_hlc(chisao_ctx *h) {
     const Dev &D = h->D;
-    hipStream_t st = h->cur;
     hipError_t e;
-    if ((e = launch_build_unfrozen(D, st)) != hipSuccess) return e;
-    if ((e = launch_sigma(D, st)) != hipSuccess) return e;
+    if ((e = launch_build_unfrozen(D, h->cur)) != hipSuccess) return e;
+    if ((e = launch_sigma(D, h->cur)) != hipSuccess) return e;
+    const size_t n = h->eclasses.size();
+    const bool forked = forks(h, n);
+    if (forked && (e = fork_open(h, n)) != hipSuccess) return e;
     const int n_cloud = max_over(h, &ProblemDesc::n_cloud);
-    for (int step = 0; step < n_cloud; ++step) {
-        if ((e = fork_join(h, h->all_e, [&](int ci, hipStream_t es) {
-                 const EvalClass &c = h->eclasses[ci];
-                 const bool adj = c.grad_mode == CHISAO_GRAD_ADJOINT;
-                 EvalArgs a = base_args(h, c);
-                 a.list_id = L_UNF;
-                 a.vc_kind = kVcProbes;
-                 a.step = step;
-                 a.need_bit = 1 << 5;
-                 a.step_limit = 1;
-                 a.nz_kind = adj ? -1 : 0;
-                 a.nz_base = kNzFdProbe;
-                 return run_eval(h, c, a, kProbe, !adj, adj, es);
-             })) != hipSuccess)
-            return e;
-        // (the finite-difference probes' mean; adjoint probes average in the kernel)
-        if (!h->fd_e.empty() && (e = launch_probe_mean(D, step, st)) != hipSuccess) return e;
-        if (step == 0 && (e = launch_step_size(D, D.Gh, 0, st)) != hipSuccess) return e;
-        if ((e = launch_hlc_update(D, step, st)) != hipSuccess) return e;
-    }
-    return hipSuccess;
+    for (int step = 0; step < n_cloud; ++step)
+        for (size_t i = 0; i < n; ++i) {
+            const EvalClass &c = h->eclasses[i];
+            const hipStream_t es = branch(h, forked, i);
+            const int np = (int)c.pids.size();
+            const bool adj = c.grad_mode == CHISAO_GRAD_ADJOINT;
+            EvalArgs a = base_args(h, c);
+            a.list_id = L_UNF;
+            a.vc_kind = kVcProbes;
+            a.step = step;
+            a.need_bit = 1 << 5;
+            a.step_limit = 1;
+            a.nz_kind = adj ? -1 : 0;
+            a.nz_base = kNzFdProbe;
+            if ((e = run_eval(h, c, a, kProbe, !adj, adj, es)) != hipSuccess) return e;
+            // (the finite-difference probes' mean; adjoint probes average in the kernel)
+            if (!adj && (e = launch_probe_mean(D, step, es, c.pids_dev, np)) != hipSuccess) return e;
+            if (step == 0 && (e = launch_step_size(D, D.Gh, 0, es, c.pids_dev, np)) != hipSuccess) return e;
+            if ((e = launch_hlc_update(D, step, es, c.pids_dev, np)) != hipSuccess) return e;
+        }
+    return forked ? fork_close(h, n) : hipSuccess;
 }
 
 static hipError_t phase_anti(chisao_ctx *h) {
     const Dev &D = h->D;
-    hipStream_t st = h->cur;
     hipError_t e;
+    const size_t n = h->eclasses.size();
+    const bool forked = forks(h, n);
+    if (forked && (e = fork_open(h, n)) != hipSuccess) return e;
     const int n_anti = max_over(h, &ProblemDesc::n_anti);
-    for (int step = 0; step < n_anti; ++step) {
-        if ((e = eval_list(h, L_UNF, nullptr, D.Gh, false, 1 << 6, 2, step, kNzFdAnti)) != hipSuccess) return e;
-        if (step == 0 && (e = launch_step_size(D, D.Gh, 1, st)) != hipSuccess) return e;
-        if ((e = launch_anti_update(D, step, st)) != hipSuccess) return e;
-    }
-    return hipSuccess;
+    for (int step = 0; step < n_anti; ++step)
+        for (size_t i = 0; i < n; ++i) {
+            const EvalClass &c = h->eclasses[i];
+            const hipStream_t es = branch(h, forked, i);
+            const int np = (int)c.pids.size();
+            if ((e = eval_list_class(h, c, es, L_UNF, nullptr, D.Gh, false, 1 << 6, 2, step, kNzFdAnti)) !=
+                hipSuccess)
+                return e;
+            if (step == 0 && (e = launch_step_size(D, D.Gh, 1, es, c.pids_dev, np)) != hipSuccess) return e;
+            if ((e = launch_anti_update(D, step, es, c.pids_dev, np)) != hipSuccess) return e;
+        }
+    return forked ? fork_close(h, n) : hipSuccess;
 }
 
 static hipError_t enqueue_phases(chisao_ctx *h, uint32_t mask) {

@@ -1223,9 +1223,9 @@ hipError_t launch_sigma(const Dev &D, hipStream_t st) {
     return hipGetLastError();
 }
 
-__global__ __launch_bounds__(kBlock) void norm_partial_kernel(Dev D, const float *Gs) {
+__global__ __launch_bounds__(kBlock) void norm_partial_kernel(Dev D, const float *Gs, const int *pids) {
     __shared__ double red[kWavesPerBlock][2];
-    const int p = blockIdx.y;
+    const int p = pids ? pids[blockIdx.y] : blockIdx.y;
     const ProblemDesc &pd = D.pd[p];
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
     const int chunk = (pd.N + gridDim.x - 1) / gridDim.x;
@@ -1271,9 +1271,10 @@ __global__ __launch_bounds__(kBlock) void norm_partial_kernel(Dev D, const float
     }
 }
 
-__global__ void step_final_kernel(Dev D, int nblocks, int which) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= D.P) return;
+__global__ void step_final_kernel(Dev D, int nblocks, int which, const int *pids, int np) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= np) return;
+    const int p = pids ? pids[i] : i;
     const ProblemDesc &pd = D.pd[p];
     double a = 0.0, n = 0.0;
     for (int b = 0; b < nblocks; ++b) {
@@ -1290,11 +1291,13 @@ __global__ void step_final_kernel(Dev D, int nblocks, int which) {
     else D.ctl[p].alpha_a = alpha;
 }
 
-hipError_t launch_step_size(const Dev &D, const float *Gsrc, int which, hipStream_t st) {
+hipError_t launch_step_size(const Dev &D, const float *Gsrc, int which, hipStream_t st, const int *pids, int np) {
     // 256 blocks per problem (2 partials each: within the partial buffer)
     constexpr int kNormBlocks = 256;
-    hipLaunchKernelGGL(norm_partial_kernel, dim3(kNormBlocks, D.P), dim3(kBlock), 0, st, D, Gsrc);
-    hipLaunchKernelGGL(step_final_kernel, dim3(grid_for(D.P, 64)), dim3(64), 0, st, D, kNormBlocks, which);
+    const int n = pids ? np : D.P;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(norm_partial_kernel, dim3(kNormBlocks, n), dim3(kBlock), 0, st, D, Gsrc, pids);
+    hipLaunchKernelGGL(step_final_kernel, dim3(grid_for(n, 64)), dim3(64), 0, st, D, kNormBlocks, which, pids, n);
     return hipGetLastError();
 }
 
@@ -1308,8 +1311,8 @@ static int per_problem_blocks(const Dev &D) {
 }
 
 // Finite-difference smoothing: mean of the per-probe gradients, probe order.
-__global__ void probe_mean_kernel(Dev D, int step) {
-    const int p = blockIdx.y;
+__global__ void probe_mean_kernel(Dev D, int step, const int *pids) {
+    const int p = pids ? pids[blockIdx.y] : blockIdx.y;
     const ProblemDesc &pd = D.pd[p];
     if (pd.grad_mode != 0 || !((pd.phase_mask >> 5) & 1) || step >= pd.n_cloud) return;
     const int n = D.ctl[p].count[L_UNF];
@@ -1323,14 +1326,16 @@ __global__ void probe_mean_kernel(Dev D, int step) {
     }
 }
 
-hipError_t launch_probe_mean(const Dev &D, int step, hipStream_t st) {
-    hipLaunchKernelGGL(probe_mean_kernel, dim3(per_problem_blocks(D), D.P), dim3(kBlock), 0, st, D, step);
+hipError_t launch_probe_mean(const Dev &D, int step, hipStream_t st, const int *pids, int np) {
+    const int n = pids ? np : D.P;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(probe_mean_kernel, dim3(per_problem_blocks(D), n), dim3(kBlock), 0, st, D, step, pids);
     return hipGetLastError();
 }
 
 // x <- clamp(x + alpha_c * smoothed gradient)
-__global__ void hlc_update_kernel(Dev D, int step) {
-    const int p = blockIdx.y;
+__global__ void hlc_update_kernel(Dev D, int step, const int *pids) {
+    const int p = pids ? pids[blockIdx.y] : blockIdx.y;
     const ProblemDesc &pd = D.pd[p];
     if (!((pd.phase_mask >> 5) & 1) || step >= pd.n_cloud) return;
     const int n = D.ctl[p].count[L_UNF];
@@ -1343,14 +1348,16 @@ __global__ void hlc_update_kernel(Dev D, int step) {
     }
 }
 
-hipError_t launch_hlc_update(const Dev &D, int step, hipStream_t st) {
-    hipLaunchKernelGGL(hlc_update_kernel, dim3(per_problem_blocks(D), D.P), dim3(kBlock), 0, st, D, step);
+hipError_t launch_hlc_update(const Dev &D, int step, hipStream_t st, const int *pids, int np) {
+    const int n = pids ? np : D.P;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(hlc_update_kernel, dim3(per_problem_blocks(D), n), dim3(kBlock), 0, st, D, step, pids);
     return hipGetLastError();
 }
 
 // v <- mu v - alpha_a g (v = 0 before the first step); x <- clamp(x + v)
-__global__ void anti_update_kernel(Dev D, int step) {
-    const int p = blockIdx.y;
+__global__ void anti_update_kernel(Dev D, int step, const int *pids) {
+    const int p = pids ? pids[blockIdx.y] : blockIdx.y;
     const ProblemDesc &pd = D.pd[p];
     if (!((pd.phase_mask >> 6) & 1) || step >= pd.n_anti) return;
     const int n = D.ctl[p].count[L_UNF];
@@ -1366,8 +1373,10 @@ __global__ void anti_update_kernel(Dev D, int step) {
     }
 }
 
-hipError_t launch_anti_update(const Dev &D, int step, hipStream_t st) {
-    hipLaunchKernelGGL(anti_update_kernel, dim3(per_problem_blocks(D), D.P), dim3(kBlock), 0, st, D, step);
+hipError_t launch_anti_update(const Dev &D, int step, hipStream_t st, const int *pids, int np) {
+    const int n = pids ? np : D.P;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(anti_update_kernel, dim3(per_problem_blocks(D), n), dim3(kBlock), 0, st, D, step, pids);
     return hipGetLastError();
 }
 

@@ -85,10 +85,13 @@ hipError_t launch_stick(const Dev &D, hipStream_t st);
 hipError_t launch_dedup(const Dev &D, hipStream_t st);
 hipError_t launch_reseed(const Dev &D, hipStream_t st);
 hipError_t launch_sigma(const Dev &D, hipStream_t st);
-hipError_t launch_probe_mean(const Dev &D, int step, hipStream_t st);
-hipError_t launch_step_size(const Dev &D, const float *Gsrc, int which, hipStream_t st);
-hipError_t launch_hlc_update(const Dev &D, int step, hipStream_t st);
-hipError_t launch_anti_update(const Dev &D, int step, hipStream_t st);
+// The per-problem exploration kernels below cover the problems pids[0 .. np)
+// (device array), or every problem when pids is null.
+hipError_t launch_probe_mean(const Dev &D, int step, hipStream_t st, const int *pids = nullptr, int np = 0);
+hipError_t launch_step_size(const Dev &D, const float *Gsrc, int which, hipStream_t st, const int *pids = nullptr,
+                            int np = 0);
+hipError_t launch_hlc_update(const Dev &D, int step, hipStream_t st, const int *pids = nullptr, int np = 0);
+hipError_t launch_anti_update(const Dev &D, int step, hipStream_t st, const int *pids = nullptr, int np = 0);
 hipError_t launch_end_cycle(const Dev &D, int advance, hipStream_t st);
 hipError_t launch_mode_list(const Dev &D, int p, int s0, int N, hipStream_t st);
 hipError_t launch_width_list(const Dev &D, int p, int N, hipStream_t st);
