@@ -120,7 +120,8 @@ typedef struct {
 } chisao_config;
 
 #define CHISAO_FLAG_NO_GRAPH 1u    /* enqueue every cycle's kernels one by one instead of replaying a captured hipGraph */
-#define CHISAO_FLAG_NO_AUTOTUNE 2u /* keep the default evaluation schedule (linear tile order, 8192 workgroups) */
+#define CHISAO_FLAG_NO_AUTOTUNE 2u /* keep the default evaluation schedule (linear tile order, 8192 workgroups,
+                                      line-search launches included) */
 /* Read per problem: when the problem's starting population is not given, draw
  * it on rays through the centre of the box from its vertices, edge midpoints
  * and face centres (the structured ray seeding of Sec. 5.3) instead of
@@ -349,7 +350,8 @@ typedef struct {
     int32_t probe_order;            /* schedule of the smoothing-probe launches: tile order */
     int32_t probe_grid_cap;         /* ... and grid size */
     float ms_probe[CHISAO_TUNE_VARIANTS]; /* measured probe-pass time per variant (0 when not tuned) */
-    int32_t trial_grid_cap;         /* grid of the line-search launches (0: the chosen grid_cap) */
+    int32_t trial_grid_cap;         /* grid of the line-search launches (0: the chosen grid_cap; always 0 with
+                                       CHISAO_FLAG_NO_AUTOTUNE) */
 } chisao_tuning_entry;
 
 /* Writes one entry per class (at most cap) and the class count to *n_out;

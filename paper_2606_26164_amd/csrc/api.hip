@@ -442,7 +442,10 @@ extern "C" int chisao_init_batched(chisao_handle *out, int n_problems, const chi
                 c.nconv = std::max(c.nconv, q.n_conv);
             }
             c.cpl = coords_per_lane(dmax);
-            c.t_grid_cap = trial_resident_blocks(c.DP, c.family, c.grad_mode == CHISAO_GRAD_ADJOINT);
+            // (CHISAO_FLAG_NO_AUTOTUNE keeps every launch at the default grid)
+            c.t_grid_cap = (h->flags & CHISAO_FLAG_NO_AUTOTUNE)
+                               ? 0
+                               : trial_resident_blocks(c.DP, c.family, c.grad_mode == CHISAO_GRAD_ADJOINT);
             h->eclasses.push_back(c);
         }
         // ---- population state ----

@@ -230,12 +230,14 @@ def test_autotuned_schedule_changes_timing_only():
             assert (t["probe_order"], t["probe_grid_cap"]) == (t["order"], t["grid_cap"])
             assert all(ms == 0 for ms in t["ms_probe"])
     # line-search launches of matrix-core mixture classes: one round of
-    # resident workgroups, whatever the flags (a rule, not a timed choice)
-    for t in tuned + fixed:
+    # resident workgroups (a rule, not a timed choice); the default grid
+    # without autotuning
+    for t in tuned:
         if t["padded_d"] == 8:
             assert t["trial_grid_cap"] == 0
         else:
             assert t["trial_grid_cap"] > 0 and t["trial_grid_cap"] % 8 == 0
+    assert all(t["trial_grid_cap"] == 0 for t in fixed)
     for t in fixed:
         assert (t["order"], t["grid_cap"]) == (0, 8192) and all(ms == 0 for ms in t["ms"])
         assert t["tile_points"] == (64 if t["padded_d"] == 8 else 32) and t["ms_half_tiles"] == t["ms_full_tiles"] == 0
@@ -260,6 +262,30 @@ def test_half_tiles_equal_full_tiles_bitwise():
     assert tiles == [(8, 1, 64), (8, 1, 64), (16, 0, 16), (64, 1, 16)]
     for p in range(len(items)):
         _assert_same(out[0][p], out[1][p], f"problem {p}: half vs full tiles")
+
+
+def test_line_search_grid_does_not_change_results():
+    """Line-search launches on one round of resident workgroups, each
+    looping over several tiles (20000 samples at d = 64: 625 tiles of 32
+    points for the first trial against 512 resident workgroups, and a d = 32
+    problem beside it), give the same bits as one workgroup per tile."""
+    from paper_2606_26164_amd import _lib as L
+    from paper_2606_26164_amd.api import Optimizer
+
+    items = []
+    for pid, (seed, d, K, N) in enumerate([(21, 64, 16, 20000), (22, 32, 12, 30000)]):
+        p = W.mixture_problem(seed, d, K, 10.0, lam_range=(0.1, 1.0))
+        c = W.RunConfig(N=N, m=6, n_osc=3, n_conv=8, M=4, eps_grad=1e-3, grad_mode=1, seed=5, problem_id=pid)
+        items.append((p, c, W.uniform_population(seed, N, p.lo, p.hi)))
+    out = []
+    for flags in (0, L.FLAG_NO_AUTOTUNE):
+        with Optimizer.batched(items, flags=flags) as opt:
+            caps = [t["trial_grid_cap"] for t in opt.tuning()]
+            opt.cycle(2)
+            out.append(([_state(opt, p) for p in range(len(items))], caps))
+    assert all(0 < c < 1000 for c in out[0][1]) and out[1][1] == [0, 0], (out[0][1], out[1][1])
+    for p in range(len(items)):
+        _assert_same(out[0][0][p], out[1][0][p], f"problem {p}: resident-round vs one-tile workgroups")
 
 
 def test_batched_closed_forms_equal_single_bitwise():
