@@ -1118,8 +1118,10 @@ static int trial_resident(bool grad) {
                                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(
                                         &nb, eval_kernel<DP, FAM, false, kTrial, false, S>, kWave * S, 0);
         if (e != hipSuccess || hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+            (void)hipGetLastError();  // no limit then; leave no error for later launches to report
             return 0;
+        }
         return nb * cus;
     }
 }
